@@ -1,0 +1,118 @@
+/*
+ * ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, obviously-correct CPU implementation of what the polynomial-
+ * filtered spectrum-slicing path computes, written from the EVSL paper (Li, Xi,
+ * Erlandson, Saad, "The Eigenvalues Slicing Library (EVSL): Algorithms,
+ * Implementation, and Software", arXiv:1802.05215). Only the test-suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it. It shares no
+ * code with the HIP library, and the HIP library never calls it.
+ *
+ * Everything is FP64. Matrices are CSR (int32 row_ptr[n+1], int32 col[nnz]
+ * ascending within a row, double val[nnz]). Blocks of vectors are row-major
+ * n x nvec unless a comment says column-major.
+ */
+#ifndef EVSL_ORACLE_H
+#define EVSL_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_DAMP_NONE 0
+#define OR_DAMP_SIGMA 1   /* Lanczos sigma factors, eq:polPJ */
+#define OR_DAMP_JACKSON 2 /* Jackson kernel (Weisse et al., Rev. Mod. Phys. 78, 275, 2006) */
+
+/* SplitMix64 output number i+1 of the generator seeded with `seed`. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t i);
+double or_uniform01(uint64_t seed, uint64_t i);
+
+/* y = A x, one row at a time, sum in column order. */
+void or_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+             const double *x, double *y);
+
+/* Damping factors g[0..k] for a degree-k Chebyshev expansion. Returns 0 or -1. */
+int or_damping(int kind, int k, double *g);
+
+/* Evaluate sum_{j=0..k} c[j] T_j(t) with T_j(t) = cos(j acos t) on [-1,1]
+ * (cosh(j acosh|t|) with the sign (-1)^j for t < -1 outside). */
+double or_cheb_series(int k, const double *c, double t);
+
+/* find_pol (Section 2.2.1, eq:mapping, eq:Cheb0, eq:mu, eq:Neq, eq:polPJ).
+ * intv = {t_i, t_{i+1}, lambda_min, lambda_max}. Writes the degree, the centre
+ * gamma, the threshold bar = rho(t_i-hat) (= rho(t_{i+1}-hat)), the map
+ * constants cc, dd, and coef[0..deg] with rho(t) = sum coef[j] T_j(t).
+ * coef must hold max_deg+1 doubles. Returns 0, 1 if max_deg was reached
+ * (filter still returned at max_deg), -1 on invalid input. */
+int or_find_pol(const double intv[4], int damping, double tau, double tau_ext,
+                int max_deg, int *deg, double *gamma, double *bar, double *cc,
+                double *dd, double *coef, int *boundary);
+
+/* Y = p(A-hat) V with p = sum_{j=0..k} coef[j] T_j and A-hat = (A - cc I)/dd,
+ * by the forward three-term Chebyshev recurrence. V, Y row-major n x nvec. */
+void or_filter_apply(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                     double cc, double dd, int k, const double *coef, int nvec,
+                     const double *V, double *Y);
+
+/* Rademacher block (row-major n x nvec): sign of output l*n+i of stream `seed`. */
+void or_rademacher(uint64_t seed, int64_t n, int nvec, double *V);
+
+/* KPM moments zeta_k = (1/nvec) sum_l v_l^T T_k(A-hat) v_l, k = 0..K, for the
+ * probe block V (row-major n x nvec). */
+void or_kpm_moments(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                    double lmin, double lmax, int K, int nvec, const double *V,
+                    double *mom);
+
+/* Estimated eigenvalue count in [x0, x1] from the damped KPM expansion. */
+double or_kpm_count(int K, const double *mom, int damping, double lmin, double lmax,
+                    double x0, double x1);
+
+/* Slicer (eq:slice-ti): cut intv[0..1] into nslices pieces of equal estimated
+ * count using an npts-point grid. sli has nslices+1 entries. Returns 0 / -1. */
+int or_slicer(int K, const double *mom, int damping, const double intv[4], int nslices,
+              int npts, double *sli);
+
+/* Cyclic Jacobi eigen-decomposition of the symmetric m x m column-major A
+ * (overwritten). w[m] ascending, Vec m x m column-major (column j = vector j). */
+int or_jacobi_eig(int m, double *A, double *w, double *Vec);
+
+/* Spectrum bounds by nsteps Lanczos steps with full reorthogonalisation from
+ * the start vector of stream `seed` (see or_lanczos_start), widened by the
+ * extreme Ritz residual estimates. */
+int or_lanczos_bounds(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                      int nsteps, uint64_t seed, double *lmin, double *lmax);
+
+/* Lanczos start vector: x_i = 2 u(seed, restart*n + i) - 1 (not normalised). */
+void or_lanczos_start(uint64_t seed, int64_t n, int64_t restart, double *x);
+
+typedef struct {
+  int m;          /* Krylov dimension per cycle */
+  int max_its;    /* cap on Lanczos steps */
+  int ncycle;     /* early-restart test period */
+  double tol;     /* residual tolerance relative to ||A|| */
+  uint64_t seed;  /* start-vector stream */
+  int nev_cap;    /* capacity of lam/res/Y */
+} or_lan_opts;
+
+typedef struct {
+  int nev;
+  int niter;      /* Lanczos steps taken */
+  int nmv;        /* products with A */
+  int nrestart;
+  int status;     /* 0 ok, 1 max_its reached, 2 capacity exceeded */
+} or_lan_stats;
+
+/* Filtered thick-restart Lanczos with locking (Algorithm alg:FiltLanTR, Section
+ * 2.5) for the slice intv = {t_i, t_{i+1}, lambda_min, lambda_max} with the
+ * filter (deg, coef, bar) from or_find_pol. Outputs lam[nev] ascending,
+ * res[nev] = ||A u - lam u|| / ||A|| and Y (n x nev_cap column-major). */
+int or_filtered_lanczos(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                        const double intv[4], int deg, const double *coef, double bar,
+                        const or_lan_opts *opt, double *lam, double *res, double *Y,
+                        or_lan_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+/*
+ * evsl_mi355 -- polynomial-filtered spectrum slicing for large sparse real
+ * symmetric matrices on one AMD MI355X (gfx950).
+ *
+ * Method: EVSL (Li, Xi, Erlandson, Saad, "The Eigenvalues Slicing Library
+ * (EVSL): Algorithms, Implementation, and Software", arXiv:1802.05215). All
+ * eigenpairs of A in [xi, eta] are found by cutting the interval into slices
+ * with a kernel-polynomial (KPM) density-of-states estimate (Section 2.1,
+ * eq:DOS0, eq:slice-ti) and running, per slice, a thick-restart Lanczos with
+ * locking on a Chebyshev polynomial filter p(A) (Section 2.2.1, Section 2.5,
+ * Algorithm alg:FiltLanTR).
+ *
+ * Conventions for every entry point:
+ *  - Return value: EVSL_OK (0) or one of the EVSL_E* codes below; no C++
+ *    exception crosses this interface. evsl_strerror() names a code.
+ *  - "device" pointers are HIP device memory on the device current when the
+ *    context was created; "host" pointers are ordinary host memory.
+ *  - Device inputs are owned by the caller, read-only, and must stay valid
+ *    until the call returns (or, for asynchronous calls, until the context's
+ *    stream has executed the work).
+ *  - The spectrum interval convention follows the paper's intv[4]
+ *    (Section 3.1): {xi, eta, lambda_min, lambda_max}.
+ */
+#ifndef EVSL_MI355_H
+#define EVSL_MI355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define EVSL_OK 0
+#define EVSL_EINVAL 1    /* bad argument: n <= 0, xi >= eta, NULL pointer, interval outside the bounds */
+#define EVSL_ENOMEM 2    /* device or host allocation failed */
+#define EVSL_EHIP 3      /* HIP runtime error (the hipError_t is kept in the context) */
+#define EVSL_EDEGREE 4   /* filter needs more than max_deg; the max_deg filter is returned */
+#define EVSL_ENOCONV 5   /* Lanczos step cap reached; the pairs locked so far are returned */
+#define EVSL_ESPECTRUM 6 /* filter blow-up: [lambda_min, lambda_max] misses part of the spectrum */
+#define EVSL_ENOTIMPL 7  /* option not implemented */
+
+/* ---- value types ---- */
+#define EVSL_F64 0
+#define EVSL_F32 1
+
+/* ---- damping of the Chebyshev expansion ---- */
+#define EVSL_DAMP_NONE 0
+#define EVSL_DAMP_SIGMA 1   /* Lanczos sigma factors, eq:polPJ (the paper's default) */
+#define EVSL_DAMP_JACKSON 2 /* Jackson kernel (Weisse et al., Rev. Mod. Phys. 78, 275, 2006) */
+
+typedef struct evsl_ctx_s *evsl_ctx_t;
+
+/* CSR matrix (Section 3.1: matrices are stored in CSR). All arrays are
+ * device memory: row_ptr[n+1] and col[nnz] int32, col ascending within a row,
+ * val[nnz] double (dtype EVSL_F64) or float (EVSL_F32). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  int dtype;
+} evsl_csr_t;
+
+/* Polynomial filter (find_pol, Section 2.2.1): rho(t) = sum_j coef[j] T_j(t)
+ * on the mapped variable t = (lambda - cc)/dd (eq:mapping). `coef` is a host
+ * buffer of `cap` doubles supplied by the caller; deg + 1 entries are used.
+ * boundary: 0 interior slice, -1 left end at lambda_min, +1 right end at
+ * lambda_max. bar is the filter value at the slice ends: Ritz values of
+ * rho(A) at or above bar are the candidates of Algorithm alg:FiltLanTR. */
+typedef struct {
+  int deg;
+  int boundary;
+  double gamma;
+  double cc;
+  double dd;
+  double bar;
+  double *coef;
+  int cap;
+} evsl_pol_t;
+
+/* Options of the filtered Lanczos (Algorithm alg:FiltLanTR). Zero fields take
+ * the documented defaults. */
+typedef struct {
+  int m;          /* Krylov dimension per cycle; 0: max(2 nev_est + 30, 60) */
+  int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) */
+  int ncycle;     /* early-restart test period; 0: 30 */
+  double tol;     /* residual tolerance ||A u - lambda u|| / ||A||; 0: 1e-8 */
+  uint64_t seed;  /* start-vector stream (SplitMix64); restarts draw further blocks */
+  int nev_est;    /* expected count in the slice (sizing only); 0: 50 */
+  int nev_cap;    /* capacity for locked pairs; 0: max(2 nev_est + 40, 100) */
+  int prec;       /* filter arithmetic: EVSL_F64, or EVSL_F32 (needs a float copy of A, see below) */
+  const void *val32; /* device float values of A, required when prec == EVSL_F32 */
+  int reserved[4];
+} evsl_lan_opts_t;
+
+/* Result of one slice. lam/res are host arrays and Y a device n x nev
+ * column-major array, all allocated by the library and released with
+ * evsl_eigs_free(). lam ascending; res[j] = ||A y_j - lam_j y_j|| / ||A|| with
+ * ||A|| = max(|lambda_min|, |lambda_max|). */
+typedef struct {
+  int nev;
+  double *lam;
+  double *res;
+  double *Y;
+  int niter;      /* Lanczos steps */
+  int nmv;        /* products with A (filter steps + Ritz checks) */
+  int nrestart;
+  int status;     /* EVSL_OK or EVSL_ENOCONV */
+  double t_mv;    /* seconds in filter products */
+  double t_orth;  /* seconds in reorthogonalisation */
+  double t_ritz;  /* seconds in Rayleigh-Ritz, locking and restarts */
+  double t_tot;
+} evsl_eigs_t;
+
+/* ---- context (replaces EVSLStart/EVSLFinish of Section 3.1) ----
+ * stream: a hipStream_t (NULL = the null stream). The context holds the
+ * stream, a grow-only device workspace, the tuning table and timers. Not
+ * thread-safe: one context per host thread and stream. */
+int evsl_create(evsl_ctx_t *ctx, void *stream);
+int evsl_destroy(evsl_ctx_t ctx);
+/* hipError_t of the last EVSL_EHIP returned by this context. */
+int evsl_last_hip_error(evsl_ctx_t ctx);
+const char *evsl_strerror(int code);
+
+/* ---- spectrum bounds (LanBounds/LanTrbounds, Section 3.1; Section 2.2.1)
+ * nsteps Lanczos steps with full reorthogonalisation from the start vector of
+ * stream `seed`; the extreme Ritz values are widened by their residual
+ * estimates |beta_{m+1} y_{m,j}|. Host outputs; synchronous. */
+int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64_t seed,
+                         double *lmin, double *lmax);
+
+/* ---- 1. KPM density of states (kpmdos, Section 2.1) ----
+ * moments[k] (host, degree+1 doubles) estimates trace T_k(A-hat),
+ * A-hat = (A - c I)/d with c, d from intv[2..3], from `nvec` Rademacher probe
+ * vectors whose signs come from SplitMix64 stream `seed` (entry (i, l) from
+ * output l*n + i). nev_est (host) is the damped estimate of the number of
+ * eigenvalues in [intv[0], intv[1]]. Synchronous. */
+int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int degree,
+                 int nvec, uint64_t seed, int damping, double *moments, double *nev_est);
+
+/* ---- 2. spectrum slicer (spslicer, eq:slice-ti) ----
+ * Host-only pure function. Cuts [intv[0], intv[1]] into nslices pieces with
+ * equal estimated counts using an npts-point uniform grid; sli (host) gets
+ * nslices+1 boundaries, sli[0] = xi, sli[nslices] = eta. */
+int evsl_slice_spectrum(const double *moments, int degree, int damping, const double intv[4],
+                        int nslices, int npts, double *sli);
+
+/* Estimated count in [x0, x1] from KPM moments (host-only). */
+int evsl_kpm_count(const double *moments, int degree, int damping, double lmin, double lmax,
+                   double x0, double x1, double *count);
+
+/* ---- 3. filter coefficients (find_pol, Section 2.2.1: eq:mapping, eq:Cheb0,
+ * eq:mu, eq:Neq, eq:polPJ) ----
+ * Host-only. intv = {t_i, t_{i+1}, lambda_min, lambda_max}. The degree is the
+ * smallest k >= 2 at which the balanced filter's end values are <= tau
+ * (interior slice) or, for a boundary slice, the inner end value is
+ * <= tau_ext. Returns EVSL_EDEGREE when max_deg is reached (the max_deg
+ * filter is still returned), EVSL_EINVAL when pol->cap < max_deg + 1. */
+int evsl_cheb_coeffs(const double intv[4], int damping, double tau, double tau_ext,
+                     int max_deg, evsl_pol_t *pol);
+
+/* ---- 4. filter application Y = p(A-hat) V (eq:Cheb0; Table tab:itercomp:
+ * k products with A for a degree-k filter) ----
+ * V, Y: device, row-major n x ncols with leading dimension ldv >= ncols, of
+ * type prec (double for EVSL_F64, float for EVSL_F32; with EVSL_F32 A must
+ * have dtype EVSL_F32). Column c uses filter pols[col_group[c]] (col_group is
+ * a host array of ncols indices < npol); all filters must share cc and dd.
+ * Columns ordered by non-increasing degree run fastest. Asynchronous on the
+ * context's stream. */
+int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
+                      const int32_t *col_group, const void *V, void *Y, int64_t ldv,
+                      int ncols, int prec);
+
+/* ---- 5. filtered thick-restart Lanczos with locking (ChebLanTr,
+ * Algorithm alg:FiltLanTR) on one slice ----
+ * intv = {t_i, t_{i+1}, lambda_min, lambda_max}; pol from evsl_cheb_coeffs
+ * on the same intv. Returns every converged eigenpair whose eigenvalue lies
+ * in [t_i, t_{i+1}] (out, allocated by the library). Synchronous. Returns
+ * EVSL_ENOCONV (with the pairs found) when max_its is reached. */
+int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4],
+                          const evsl_pol_t *pol, const evsl_lan_opts_t *opt, evsl_eigs_t *out);
+
+/* Several slices of one matrix solved together: each Lanczos step applies all
+ * active slices' filters in one block SpMM launch per degree step (columns
+ * are slices, ordered by degree). intv holds 4 doubles per slice; pols and
+ * outs one entry per slice; opts one entry per slice. Synchronous. */
+int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices,
+                                const double *intv, const evsl_pol_t *pols,
+                                const evsl_lan_opts_t *opts, evsl_eigs_t *outs);
+
+/* Copies the result vectors into a caller-owned device array dst (column j
+ * of out->Y to dst + j*ldd, ldd >= n). Asynchronous on the context stream. */
+int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, double *dst,
+                          int64_t ldd);
+
+/* Releases lam, res (host) and Y (device) of a result; safe on zeroed structs. */
+void evsl_eigs_free(evsl_ctx_t ctx, evsl_eigs_t *out);
+
+/* ---- measurement helpers ----
+ * Number of filter-step kernels launched and their total device time (from
+ * HIP events on the context stream) since the last reset. */
+int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes);
+int evsl_reset_stats(evsl_ctx_t ctx);
+/* Enables (1) or disables (0) HIP-event timing of each filter application. */
+int evsl_set_timing(evsl_ctx_t ctx, int on);
+/* Selects the SpMV variant for single-vector filter steps: 0 auto, 1 direct
+ * row-per-thread, 2 LDS-staged CSR stream. */
+int evsl_set_spmv_variant(evsl_ctx_t ctx, int variant);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

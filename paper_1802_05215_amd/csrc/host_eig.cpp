@@ -1,0 +1,128 @@
+// Dense symmetric eigensolver for the small projected matrices of the
+// Lanczos process (T_m of eq:Tm, tridiagonal, or arrowhead plus tridiagonal
+// after a thick restart). Householder reduction to tridiagonal form, then
+// implicit symmetric QR steps with the Wilkinson shift and bulge chasing by
+// Givens rotations (Golub and Van Loan, Matrix Computations, 8.3.1-8.3.3).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "host_poly.hpp"
+
+namespace evh {
+
+int sym_eig(int m, double *A, double *w, double *V) {
+  if (m <= 0) return -1;
+  auto a = [&](int i, int j) -> double & { return A[i + (size_t)j * m]; };
+  if (V) {
+    std::fill(V, V + (size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) V[i + (size_t)i * m] = 1.0;
+  }
+  std::vector<double> v(m), p(m), q(m);
+  // --- Householder tridiagonalisation: column k below the subdiagonal is zeroed
+  for (int k = 0; k + 2 < m; ++k) {
+    const int len = m - k - 1;
+    double sig = 0.0;
+    for (int i = 0; i < len; ++i) sig += a(k + 1 + i, k) * a(k + 1 + i, k);
+    if (sig == 0.0) continue;
+    const double x0 = a(k + 1, k);
+    const double alpha = x0 >= 0 ? -std::sqrt(sig) : std::sqrt(sig);
+    for (int i = 0; i < len; ++i) v[i] = a(k + 1 + i, k);
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (int i = 0; i < len; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // p = beta * A22 v
+    for (int i = 0; i < len; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < len; ++j) s += a(k + 1 + i, k + 1 + j) * v[j];
+      p[i] = beta * s;
+    }
+    double pv = 0.0;
+    for (int i = 0; i < len; ++i) pv += p[i] * v[i];
+    const double kk = 0.5 * beta * pv;
+    for (int i = 0; i < len; ++i) q[i] = p[i] - kk * v[i];
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < len; ++i) a(k + 1 + i, k + 1 + j) -= v[i] * q[j] + q[i] * v[j];
+    a(k + 1, k) = alpha;
+    a(k, k + 1) = alpha;
+    for (int i = 1; i < len; ++i) {
+      a(k + 1 + i, k) = 0.0;
+      a(k, k + 1 + i) = 0.0;
+    }
+    if (V) {  // V <- V (I - beta v v^T) on columns k+1..m-1
+      for (int r = 0; r < m; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < len; ++i) s += V[r + (size_t)(k + 1 + i) * m] * v[i];
+        s *= beta;
+        for (int i = 0; i < len; ++i) V[r + (size_t)(k + 1 + i) * m] -= s * v[i];
+      }
+    }
+  }
+  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+  for (int i = 0; i < m; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < m; ++i) e[i] = a(i + 1, i);
+  // --- implicit QR on the tridiagonal (d, e)
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1;
+  for (long iter = 0; hi > 0 && iter < 60L * m + 100; ++iter) {
+    // deflate converged trailing entries
+    while (hi > 0 && std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi])) * 0.5) {
+      e[hi - 1] = 0.0;
+      --hi;
+    }
+    if (hi == 0) break;
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo])) * 0.5)
+      --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    // Wilkinson shift from the trailing 2 x 2 block
+    const double del = 0.5 * (d[hi - 1] - d[hi]);
+    const double e2 = e[hi - 1] * e[hi - 1];
+    const double sgn = del >= 0 ? 1.0 : -1.0;
+    const double mu = d[hi] - e2 / (del + sgn * std::sqrt(del * del + e2));
+    double x = d[lo] - mu, z = e[lo];
+    double bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double c = r == 0.0 ? 1.0 : x / r;
+      const double s = r == 0.0 ? 0.0 : -z / r;
+      if (k > lo) e[k - 1] = r;
+      // rotate the 2 x 2 block (k, k+1): G^T B G with G = [[c, s], [-s, c]]
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = dk * c * c - 2.0 * ek * c * s + dk1 * s * s;
+      d[k + 1] = dk * s * s + 2.0 * ek * c * s + dk1 * c * c;
+      e[k] = (dk - dk1) * c * s + ek * (c * c - s * s);
+      if (k + 1 < hi) {
+        bulge = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      if (V) {
+        double *vk = V + (size_t)k * m, *vk1 = V + (size_t)(k + 1) * m;
+        for (int r2 = 0; r2 < m; ++r2) {
+          const double t0 = vk[r2], t1 = vk1[r2];
+          vk[r2] = c * t0 - s * t1;
+          vk1[r2] = s * t0 + c * t1;
+        }
+      }
+      x = e[k];
+      z = bulge;
+    }
+  }
+  // --- sort ascending
+  std::vector<int> idx(m);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return d[i] < d[j]; });
+  for (int i = 0; i < m; ++i) w[i] = d[idx[i]];
+  if (V) {
+    std::vector<double> tmp((size_t)m * m);
+    for (int j = 0; j < m; ++j)
+      std::copy(V + (size_t)idx[j] * m, V + (size_t)idx[j] * m + m, tmp.begin() + (size_t)j * m);
+    std::copy(tmp.begin(), tmp.end(), V);
+  }
+  return 0;
+}
+
+}  // namespace evh

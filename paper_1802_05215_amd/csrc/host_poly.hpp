@@ -1,0 +1,30 @@
+// Host-side polynomial work: damping, find_pol, KPM count, slicer.
+#pragma once
+
+namespace evh {
+
+struct FilterOut {
+  int deg;
+  int boundary;
+  double gamma, cc, dd, bar;
+  double *coef;  // caller buffer of max_deg + 1
+};
+
+// kind: 0 none, 1 Lanczos sigma (eq:polPJ), 2 Jackson. g has k+1 entries.
+int damping_factors(int kind, int k, double *g);
+// 0: found, 1: max_deg reached (max_deg filter returned), -1: invalid.
+int find_filter(const double intv[4], int damp, double tau, double tau_ext, int max_deg,
+                FilterOut *out);
+// g: damping factors for degree K; c, d: spectrum map.
+double kpm_count(int K, const double *mom, const double *g, double c, double d, double x0,
+                 double x1);
+int slice(int K, const double *mom, int damp, const double intv[4], int nslices, int npts,
+          double *sli);
+
+// Symmetric eigen-decomposition of the m x m column-major A (overwritten):
+// Householder tridiagonalisation, then implicit QR steps with Wilkinson
+// shifts (Golub and Van Loan, Sections 8.3.1-8.3.3). w ascending; V (m x m,
+// column-major, may be null for eigenvalues only).
+int sym_eig(int m, double *A, double *w, double *V);
+
+}  // namespace evh

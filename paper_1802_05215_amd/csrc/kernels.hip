@@ -1,0 +1,569 @@
+// HIP kernels for gfx950 (MI355X): the Chebyshev filter recurrence over CSR
+// (Section 2.2.1, eq:Cheb0, eq:mapping), the reductions of the Lanczos step
+// (eq:3term with full reorthogonalisation, Section 2.3), and helpers.
+//
+// All reductions use a fixed order (per-lane sums in index order, a fixed
+// butterfly inside the 64-wide wavefront, wave partials summed in wave order,
+// then workgroup partials summed in workgroup order), so every result is
+// reproducible bit for bit for a given problem size and launch shape.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace evk {
+
+static constexpr int TPB = 256;  // 4 wavefronts of 64
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup; valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds4[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  return s;
+}
+
+// ---------------------------------------------------------------- SplitMix64
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------- filter step, single vectors
+// One row per thread; grid.y selects the column of a column-major multivector.
+template <typename T, int KIND>
+__global__ __launch_bounds__(TPB) void k_cheb_vec_direct(int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci,
+                                                         const T *__restrict__ va, T s1, T s0,
+                                                         const T *__restrict__ W, const T *Wp,
+                                                         T *Wn, T *Y, int64_t ld,
+                                                         const double *__restrict__ coef,
+                                                         int cld, int jnext) {
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+  constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
+  constexpr bool Y_INIT = (KIND == STEP_FIRST);
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  if (r >= n) return;
+  const int64_t off = (int64_t)blockIdx.y * ld;
+  const T *w = W + off;
+  T acc = 0;
+  const int kb = rp[r], ke = rp[r + 1];
+  for (int k = kb; k < ke; ++k) acc += va[k] * w[ci[k]];
+  const T wr = w[r];
+  T wn = s1 * acc + s0 * wr;
+  if (HAS_PREV) wn -= Wp[off + r];
+  Wn[off + r] = wn;
+  if (HAS_Y) {
+    const double *cc = coef + (int64_t)blockIdx.y * cld;
+    const T y = Y_INIT ? (T)cc[0] * wr : Y[off + r];
+    Y[off + r] = y + (T)cc[jnext] * wn;
+  }
+}
+
+// LDS-staged CSR stream: the workgroup's 256 rows of row_ptr, col and val are
+// loaded into LDS with coalesced loads, then each thread sums its row from LDS.
+// Falls back to direct reads when the rows hold more than CAP entries.
+template <typename T, int KIND>
+__global__ __launch_bounds__(TPB) void k_cheb_vec_lds(int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const T *__restrict__ va, T s1, T s0,
+                                                      const T *__restrict__ W, const T *Wp, T *Wn,
+                                                      T *Y, int64_t ld,
+                                                      const double *__restrict__ coef, int cld,
+                                                      int jnext) {
+  constexpr int CAP = 2048;
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+  constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
+  constexpr bool Y_INIT = (KIND == STEP_FIRST);
+  __shared__ int s_rp[TPB + 1];
+  __shared__ int s_ci[CAP];
+  __shared__ T s_va[CAP];
+  const int r0 = blockIdx.x * TPB;
+  const int nr = min(TPB, n - r0);
+  for (int i = threadIdx.x; i <= nr; i += TPB) s_rp[i] = rp[r0 + i];
+  __syncthreads();
+  const int nz0 = s_rp[0];
+  const int cnt = s_rp[nr] - nz0;
+  const bool staged = cnt <= CAP;
+  if (staged) {
+    for (int i = threadIdx.x; i < cnt; i += TPB) {
+      s_ci[i] = ci[nz0 + i];
+      s_va[i] = va[nz0 + i];
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= nr) return;
+  const int r = r0 + t;
+  const int64_t off = (int64_t)blockIdx.y * ld;
+  const T *w = W + off;
+  T acc = 0;
+  const int kb = s_rp[t], ke = s_rp[t + 1];
+  if (staged) {
+    for (int k = kb - nz0; k < ke - nz0; ++k) acc += s_va[k] * w[s_ci[k]];
+  } else {
+    for (int k = kb; k < ke; ++k) acc += va[k] * w[ci[k]];
+  }
+  const T wr = w[r];
+  T wn = s1 * acc + s0 * wr;
+  if (HAS_PREV) wn -= Wp[off + r];
+  Wn[off + r] = wn;
+  if (HAS_Y) {
+    const double *cc = coef + (int64_t)blockIdx.y * cld;
+    const T y = Y_INIT ? (T)cc[0] * wr : Y[off + r];
+    Y[off + r] = y + (T)cc[jnext] * wn;
+  }
+}
+
+template <typename T>
+void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, double s0,
+              const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
+              int cld, int jnext) {
+  if (A.n <= 0 || ncol <= 0) return;
+  dim3 grid((A.n + TPB - 1) / TPB, ncol);
+  const T *va = (const T *)A.va;
+#define EVK_LAUNCH_VEC(KERN, K)                                                               \
+  hipLaunchKernelGGL((KERN<T, K>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, \
+                     Wp, Wn, Y, ld, coef, cld, jnext)
+  if (variant == 2) {
+    switch (kind) {
+      case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_PLAIN); break;
+      case STEP_FIRST: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_FIRST); break;
+      default: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_NEXT); break;
+    }
+  } else {
+    switch (kind) {
+      case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_PLAIN); break;
+      case STEP_FIRST: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_FIRST); break;
+      default: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_NEXT); break;
+    }
+  }
+#undef EVK_LAUNCH_VEC
+}
+
+template void cheb_vec<double>(hipStream_t, const Csr &, int, int, double, double, const double *,
+                               const double *, double *, double *, int64_t, int, const double *,
+                               int, int);
+template void cheb_vec<float>(hipStream_t, const Csr &, int, int, double, double, const float *,
+                              const float *, float *, float *, int64_t, int, const double *, int,
+                              int);
+
+// ---------------------------------------------------------------- filter step, row-major block
+// Row-major n x ld block, the first nc columns active. With nc <= 256 a
+// workgroup covers 256/nc rows per pass (lanes of a row read nc contiguous
+// values of each gathered row); wider blocks split the columns over grid.y.
+template <typename T, int KIND>
+__global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg,
+                                                  const int *__restrict__ rp,
+                                                  const int *__restrict__ ci,
+                                                  const T *__restrict__ va, T s1, T s0,
+                                                  const T *__restrict__ W, const T *Wp, T *Wn,
+                                                  T *Y, int64_t ld,
+                                                  const double *__restrict__ coef, int cld,
+                                                  int jnext, const T *__restrict__ Vd,
+                                                  double *partial) {
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT);
+  constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
+  constexpr bool Y_INIT = (KIND == STEP_FIRST);
+  constexpr bool HAS_DOT = (KIND == STEP_KPM_FIRST || KIND == STEP_KPM_NEXT);
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  int R0, rsub, col;
+  bool active;
+  if (nc <= TPB) {
+    R0 = TPB / nc;
+    rsub = tid / nc;
+    col = tid - rsub * nc;
+    active = rsub < R0;
+  } else {
+    R0 = 1;
+    rsub = 0;
+    col = blockIdx.y * TPB + tid;
+    active = col < nc;
+  }
+  double dacc = 0.0;
+  if (active) {
+    T c0 = 0, c1 = 0;
+    if (HAS_Y) {
+      c1 = (T)coef[(int64_t)col * cld + jnext];
+      if (Y_INIT) c0 = (T)coef[(int64_t)col * cld];
+    }
+    const int rbeg = blockIdx.x * rows_per_wg;
+    const int rend = min(rbeg + rows_per_wg, n);
+    for (int r = rbeg + rsub; r < rend; r += R0) {
+      T acc = 0;
+      const int kb = rp[r], ke = rp[r + 1];
+      for (int k = kb; k < ke; ++k) acc += va[k] * W[(int64_t)ci[k] * ld + col];
+      const int64_t e = (int64_t)r * ld + col;
+      const T w = W[e];
+      T wn = s1 * acc + s0 * w;
+      if (HAS_PREV) wn -= Wp[e];
+      Wn[e] = wn;
+      if (HAS_Y) {
+        const T y = Y_INIT ? c0 * w : Y[e];
+        Y[e] = y + c1 * wn;
+      }
+      if (HAS_DOT) dacc += (double)Vd[e] * (double)wn;
+    }
+  }
+  if (HAS_DOT) {
+    const double b = block_sum(dacc, red);
+    if (tid == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+static void blk_shape(int n, int nc, int *rows_per_wg, dim3 *grid) {
+  int R0 = nc <= TPB ? TPB / nc : 1;
+  int passes = 4;
+  *rows_per_wg = R0 * passes;
+  int gx = (n + *rows_per_wg - 1) / *rows_per_wg;
+  int gy = nc <= TPB ? 1 : (nc + TPB - 1) / TPB;
+  *grid = dim3(gx, gy);
+}
+
+int blk_partials(int n, int nc) {
+  int rpw;
+  dim3 g;
+  blk_shape(n, nc, &rpw, &g);
+  return (int)(g.x * g.y);
+}
+
+template <typename T>
+void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const T *W,
+              const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
+              const T *Vd, double *partial) {
+  if (A.n <= 0 || nc <= 0) return;
+  int rpw;
+  dim3 grid;
+  blk_shape(A.n, nc, &rpw, &grid);
+  const T *va = (const T *)A.va;
+#define EVK_LAUNCH_BLK(K)                                                                       \
+  hipLaunchKernelGGL((k_cheb_blk<T, K>), grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, \
+                     (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd, partial)
+  switch (kind) {
+    case STEP_PLAIN: EVK_LAUNCH_BLK(STEP_PLAIN); break;
+    case STEP_FIRST: EVK_LAUNCH_BLK(STEP_FIRST); break;
+    case STEP_NEXT: EVK_LAUNCH_BLK(STEP_NEXT); break;
+    case STEP_KPM_FIRST: EVK_LAUNCH_BLK(STEP_KPM_FIRST); break;
+    default: EVK_LAUNCH_BLK(STEP_KPM_NEXT); break;
+  }
+#undef EVK_LAUNCH_BLK
+}
+
+template void cheb_blk<double>(hipStream_t, const Csr &, int, double, double, const double *,
+                               const double *, double *, double *, int64_t, int, const double *,
+                               int, int, const double *, double *);
+template void cheb_blk<float>(hipStream_t, const Csr &, int, double, double, const float *,
+                              const float *, float *, float *, int64_t, int, const double *, int,
+                              int, const float *, double *);
+
+// ---------------------------------------------------------------- gather / scatter
+__global__ __launch_bounds__(TPB) void k_gather_cols(int n, int nc, const double *const *src,
+                                                     double *blk, int64_t ldb) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= (int64_t)n * nc) return;
+  const int r = (int)(e / nc), c = (int)(e - (int64_t)r * nc);
+  blk[(int64_t)r * ldb + c] = src[c][r];
+}
+
+__global__ __launch_bounds__(TPB) void k_scatter_cols(int n, int nc, const double *blk,
+                                                      int64_t ldb, double *const *dst) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= (int64_t)n * nc) return;
+  const int r = (int)(e / nc), c = (int)(e - (int64_t)r * nc);
+  dst[c][r] = blk[(int64_t)r * ldb + c];
+}
+
+void gather_cols(hipStream_t s, int n, int nc, const double *const *src, double *blk,
+                 int64_t ldb) {
+  int64_t tot = (int64_t)n * nc;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s, n,
+                     nc, src, blk, ldb);
+}
+
+void scatter_cols(hipStream_t s, int n, int nc, const double *blk, int64_t ldb,
+                  double *const *dst) {
+  int64_t tot = (int64_t)n * nc;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s,
+                     n, nc, blk, ldb, dst);
+}
+
+// ---------------------------------------------------------------- reductions over columns
+// out[c] = scale * sum_w partial[c * nw + w]; one workgroup per column.
+__global__ __launch_bounds__(TPB) void k_reduce_partials(int nw, const double *partial,
+                                                         double scale, double *out) {
+  __shared__ double red[4];
+  const double *p = partial + (int64_t)blockIdx.x * nw;
+  double acc = 0.0;
+  for (int w = threadIdx.x; w < nw; w += TPB) acc += p[w];
+  const double b = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = scale * b;
+}
+
+void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
+                     double *out) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_reduce_partials, dim3(ncol), dim3(TPB), 0, s, nw, partial, scale, out);
+}
+
+// h = B^T z, partial sums per 64*RPL-row chunk; wave w of the workgroup takes
+// columns j = w, w+4, ...; z of the chunk stays in registers.
+static constexpr int GEMV_RPL = 16;
+static constexpr int GEMV_ROWS = 64 * GEMV_RPL;
+
+__global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const double *__restrict__ B,
+                                                        int64_t ld, const double *__restrict__ z,
+                                                        double *partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * GEMV_ROWS;
+  double zr[GEMV_RPL];
+#pragma unroll
+  for (int t = 0; t < GEMV_RPL; ++t) {
+    const int r = r0 + lane + 64 * t;
+    zr[t] = r < n ? z[r] : 0.0;
+  }
+  const int nwg = gridDim.x;
+  for (int j = wave; j < nb; j += 4) {
+    const double *b = B + (int64_t)j * ld;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < GEMV_RPL; ++t) {
+      const int r = r0 + lane + 64 * t;
+      if (r < n) acc += b[r] * zr[t];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) partial[(int64_t)j * nwg + blockIdx.x] = acc;
+  }
+}
+
+int gemv_partials(int n, int nb) { return ((n + GEMV_ROWS - 1) / GEMV_ROWS) * std::max(nb, 1); }
+
+void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *z,
+            double *partial, double *h) {
+  if (nb <= 0 || n <= 0) return;
+  const int nwg = (n + GEMV_ROWS - 1) / GEMV_ROWS;
+  hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg), dim3(TPB), 0, s, n, nb, B, ld, z, partial);
+  reduce_partials(s, nwg, nb, partial, 1.0, h);
+}
+
+// z -= B h, one row per thread, h staged through LDS in chunks.
+__global__ __launch_bounds__(TPB) void k_gemv_n_sub(int n, int nb, const double *__restrict__ B,
+                                                    int64_t ld, const double *__restrict__ h,
+                                                    double *z) {
+  __shared__ double sh[1024];
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < nb; j0 += 1024) {
+    const int cnt = min(1024, nb - j0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += TPB) sh[i] = h[j0 + i];
+    __syncthreads();
+    if (r < n) {
+      const double *b = B + (int64_t)j0 * ld + r;
+#pragma unroll 8
+      for (int j = 0; j < cnt; ++j) acc += b[(int64_t)j * ld] * sh[j];
+    }
+  }
+  if (r < n) z[r] -= acc;
+}
+
+void gemv_n_sub(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
+                double *z) {
+  if (nb <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, nb, B, ld, h,
+                     z);
+}
+
+// Column dots and residual norms: 2048-row chunks, grid.y over columns.
+static constexpr int DOT_ROWS = 2048;
+
+__global__ __launch_bounds__(TPB) void k_col_dots(int n, const double *__restrict__ X, int64_t ldx,
+                                                  const double *__restrict__ Y, int64_t ldy,
+                                                  double *partial) {
+  __shared__ double red[4];
+  const double *x = X + (int64_t)blockIdx.y * ldx;
+  const double *y = Y + (int64_t)blockIdx.y * ldy;
+  const int r0 = blockIdx.x * DOT_ROWS;
+  const int r1 = min(r0 + DOT_ROWS, n);
+  double acc = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += TPB) acc += x[r] * y[r];
+  const double b = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = b;
+}
+
+int dot_partials(int n, int ncol) { return ((n + DOT_ROWS - 1) / DOT_ROWS) * std::max(ncol, 1); }
+
+void col_dots(hipStream_t s, int n, int ncol, const double *X, int64_t ldx, const double *Y,
+              int64_t ldy, double *partial, double *out) {
+  if (ncol <= 0 || n <= 0) return;
+  const int nwg = (n + DOT_ROWS - 1) / DOT_ROWS;
+  hipLaunchKernelGGL(k_col_dots, dim3(nwg, ncol), dim3(TPB), 0, s, n, X, ldx, Y, ldy, partial);
+  reduce_partials(s, nwg, ncol, partial, 1.0, out);
+}
+
+__global__ __launch_bounds__(TPB) void k_col_resid2(int n, const double *__restrict__ X,
+                                                    const double *__restrict__ AX, int64_t ld,
+                                                    const double *__restrict__ xax,
+                                                    const double *__restrict__ xx,
+                                                    double *partial) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const double lam = xax[c] / xx[c];
+  const double *x = X + (int64_t)c * ld;
+  const double *ax = AX + (int64_t)c * ld;
+  const int r0 = blockIdx.x * DOT_ROWS;
+  const int r1 = min(r0 + DOT_ROWS, n);
+  double acc = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += TPB) {
+    const double e = ax[r] - lam * x[r];
+    acc += e * e;
+  }
+  const double b = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)c * gridDim.x + blockIdx.x] = b;
+}
+
+void col_resid2(hipStream_t s, int n, int ncol, const double *X, const double *AX, int64_t ld,
+                const double *xax, const double *xx, double *partial, double *out) {
+  if (ncol <= 0 || n <= 0) return;
+  const int nwg = (n + DOT_ROWS - 1) / DOT_ROWS;
+  hipLaunchKernelGGL(k_col_resid2, dim3(nwg, ncol), dim3(TPB), 0, s, n, X, AX, ld, xax, xx,
+                     partial);
+  reduce_partials(s, nwg, ncol, partial, 1.0, out);
+}
+
+// ---------------------------------------------------------------- scaling
+__global__ __launch_bounds__(TPB) void k_normalize(int n, const double *src, double *dst,
+                                                   const double *__restrict__ nrm2,
+                                                   double *beta_out) {
+  const double beta = sqrt(nrm2[0]);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  if (beta_out != nullptr && r == 0) beta_out[0] = beta;
+  if (r < n) dst[r] = src[r] * inv;
+}
+
+void normalize(hipStream_t s, int n, const double *src, double *dst, const double *nrm2,
+               double *beta_out) {
+  hipLaunchKernelGGL(k_normalize, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, src, dst, nrm2,
+                     beta_out);
+}
+
+__global__ __launch_bounds__(TPB) void k_normalize_cols(int n, double *X, int64_t ld,
+                                                        const double *__restrict__ nrm2) {
+  const int c = blockIdx.y;
+  const double beta = sqrt(nrm2[c]);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  if (r < n) X[(int64_t)c * ld + r] *= inv;
+}
+
+void normalize_cols(hipStream_t s, int n, int ncol, double *X, int64_t ld, const double *nrm2) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_normalize_cols, dim3((n + TPB - 1) / TPB, ncol), dim3(TPB), 0, s, n, X, ld,
+                     nrm2);
+}
+
+// ---------------------------------------------------------------- C = A B (tall A, small B)
+// 256 rows of C per workgroup and 16 columns per grid.y slice; B staged in LDS
+// 256 rows of K at a time.
+__global__ __launch_bounds__(TPB) void k_gemm_nn(int n, int K, int N, const double *__restrict__ A,
+                                                 int64_t lda, const double *__restrict__ B,
+                                                 int64_t ldb, double *C, int64_t ldc) {
+  __shared__ double Bs[256][16];
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  const int j0 = blockIdx.y * 16;
+  const int nj = min(16, N - j0);
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 256) {
+    const int kc = min(256, K - k0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kc * 16; idx += TPB) {
+      const int kk = idx >> 4, jj = idx & 15;
+      Bs[kk][jj] = (jj < nj) ? B[(int64_t)(k0 + kk) + (int64_t)(j0 + jj) * ldb] : 0.0;
+    }
+    __syncthreads();
+    if (r < n) {
+      const double *a = A + (int64_t)k0 * lda + r;
+      for (int kk = 0; kk < kc; ++kk) {
+        const double av = a[(int64_t)kk * lda];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += av * Bs[kk][j];
+      }
+    }
+  }
+  if (r < n) {
+    for (int j = 0; j < nj; ++j) C[(int64_t)(j0 + j) * ldc + r] = acc[j];
+  }
+}
+
+void gemm_nn(hipStream_t s, int n, int K, int N, const double *A, int64_t lda, const double *B,
+             int64_t ldb, double *C, int64_t ldc) {
+  if (n <= 0 || N <= 0) return;
+  hipLaunchKernelGGL(k_gemm_nn, dim3((n + TPB - 1) / TPB, (N + 15) / 16), dim3(TPB), 0, s, n, K, N,
+                     A, lda, B, ldb, C, ldc);
+}
+
+// ---------------------------------------------------------------- random inputs
+__global__ __launch_bounds__(TPB) void k_rademacher(int n, int nvec, uint64_t seed, double *V) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= (int64_t)n * nvec) return;
+  const int64_t i = e / nvec;
+  const int64_t l = e - i * nvec;
+  const uint64_t bits = sm64(seed, (uint64_t)l * (uint64_t)n + (uint64_t)i) >> 63;
+  V[e] = bits ? -1.0 : 1.0;
+}
+
+void rademacher(hipStream_t s, int n, int nvec, uint64_t seed, double *V) {
+  const int64_t tot = (int64_t)n * nvec;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_rademacher, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s, n,
+                     nvec, seed, V);
+}
+
+__global__ __launch_bounds__(TPB) void k_lanczos_start(int n, uint64_t seed, int64_t restart,
+                                                       double *x) {
+  const int i = blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t u = sm64(seed, (uint64_t)restart * (uint64_t)n + (uint64_t)i) >> 11;
+  x[i] = 2.0 * ((double)u * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
+void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double *x) {
+  hipLaunchKernelGGL(k_lanczos_start, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, seed, restart,
+                     x);
+}
+
+// ---------------------------------------------------------------- conversions
+__global__ __launch_bounds__(TPB) void k_to_f32(int64_t n, const double *x, float *y) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ __launch_bounds__(TPB) void k_to_f64(int64_t n, const float *x, double *y) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+void to_f32(hipStream_t s, int64_t n, const double *x, float *y) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, n, x, y);
+}
+void to_f64(hipStream_t s, int64_t n, const float *x, double *y) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, n, x, y);
+}
+
+}  // namespace evk

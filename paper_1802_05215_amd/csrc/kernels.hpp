@@ -1,0 +1,81 @@
+// Internal launch interface of the HIP kernels (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace evk {
+
+struct Csr {
+  int n;
+  int64_t nnz;
+  const int *rp;
+  const int *ci;
+  const void *va;
+  int dtype;  // 0 double, 1 float
+};
+
+// Step kinds of the three-term Chebyshev recurrence (eq:Cheb0) on
+// A-hat = (A - c I)/d:
+//   PLAIN: Wn = s1 * A W + s0 * W                      (no Y)
+//   FIRST: Wn = s1 * A W + s0 * W, Y = c0 W + c1 Wn    (s1 = 1/d, s0 = -c/d)
+//   NEXT : Wn = s1 * A W + s0 * W - Wp, Y += c Wn     (s1 = 2/d, s0 = -2c/d)
+// Wn may alias Wp (each element is read, then written, by one thread).
+enum StepKind { STEP_PLAIN = 0, STEP_FIRST = 1, STEP_NEXT = 2, STEP_KPM_FIRST = 3, STEP_KPM_NEXT = 4 };
+
+// Single vectors stored as columns of a column-major array (column stride ld);
+// grid.y runs over ncol columns. coef: device table, column c uses
+// coef[c * cld + j]. variant: 1 direct (row per thread), 2 LDS-staged.
+template <typename T>
+void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, double s0,
+              const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
+              int cld, int jnext);
+
+// Row-major block n x ld, first nc columns active. For the KPM kinds, Vd is
+// the probe block and partial receives one partial sum of Vd . Wn per
+// workgroup (partial must hold blk_partials(n, nc) doubles).
+template <typename T>
+void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const T *W,
+              const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
+              const T *Vd, double *partial);
+int blk_partials(int n, int nc);
+
+// Gather / scatter single columns into / out of a row-major block:
+// blk[r * ldb + c] = src[c][r] for c < nc (pointers in a device array).
+void gather_cols(hipStream_t s, int n, int nc, const double *const *src, double *blk, int64_t ldb);
+void scatter_cols(hipStream_t s, int n, int nc, const double *blk, int64_t ldb, double *const *dst);
+
+// h[j] = B[:, j] . z  for j < nb (B column-major, leading dim ld); uses
+// `partial` (gemv_partials(n, nb) doubles). Deterministic order.
+int gemv_partials(int n, int nb);
+void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *z,
+            double *partial, double *h);
+// z -= B h
+void gemv_n_sub(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
+                double *z);
+// out[c] = X[:, c] . Y[:, c] for c < ncol (column-major, strides ldx, ldy).
+int dot_partials(int n, int ncol);
+void col_dots(hipStream_t s, int n, int ncol, const double *X, int64_t ldx, const double *Y,
+              int64_t ldy, double *partial, double *out);
+// out[c] = || AX[:, c] - lam_c X[:, c] ||^2 with lam_c = xax[c] / xx[c].
+void col_resid2(hipStream_t s, int n, int ncol, const double *X, const double *AX, int64_t ld,
+                const double *xax, const double *xx, double *partial, double *out);
+// dst = src / sqrt(nrm2[0]); beta_out[0] = sqrt(nrm2[0]) when beta_out != nullptr.
+void normalize(hipStream_t s, int n, const double *src, double *dst, const double *nrm2,
+               double *beta_out);
+// X[:, c] *= 1/sqrt(nrm2[c]) for c < ncol.
+void normalize_cols(hipStream_t s, int n, int ncol, double *X, int64_t ld, const double *nrm2);
+// C = A B: A n x K column-major (lda), B K x N column-major (ldb), C n x N (ldc).
+void gemm_nn(hipStream_t s, int n, int K, int N, const double *A, int64_t lda, const double *B,
+             int64_t ldb, double *C, int64_t ldc);
+// Counter-based random numbers (SplitMix64 output index + 1 from state seed).
+void rademacher(hipStream_t s, int n, int nvec, uint64_t seed, double *V);
+void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double *x);
+// Final fixed-order reduction of nw partial sums per column:
+// out[c] = scale * sum_w partial[c * nw + w].
+void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
+                     double *out);
+// y = float(x) / x = double(y)
+void to_f32(hipStream_t s, int64_t n, const double *x, float *y);
+void to_f64(hipStream_t s, int64_t n, const float *x, double *y);
+
+}  // namespace evk

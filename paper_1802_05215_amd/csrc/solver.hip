@@ -1,0 +1,1115 @@
+// C-ABI of the library and the host orchestration around the HIP kernels:
+// context, spectrum bounds, KPM moments, filter application, and the filtered
+// thick-restart Lanczos with locking (Algorithm alg:FiltLanTR, Section 2.5),
+// single slice and several slices in lock-step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/evsl_mi355.h"
+#include "host_poly.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+struct Error {
+  int code;
+};
+
+[[noreturn]] void fail(int code) { throw Error{code}; }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct evsl_ctx_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int last_hip = 0;
+  int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged
+  bool timing = true;
+  // filter measurement
+  int64_t filt_launches = 0;
+  double filt_seconds = 0.0;
+  double filt_bytes = 0.0;
+  struct Pending {
+    hipEvent_t a, b;
+    int64_t launches;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  // grow-only workspace slots
+  std::vector<void *> ws_ptr;
+  std::vector<size_t> ws_size;
+  double *pinned = nullptr;
+  size_t pinned_cap = 0;
+};
+
+namespace {
+
+void hipchk(evsl_ctx_t ctx, hipError_t e) {
+  if (e != hipSuccess) {
+    if (ctx) ctx->last_hip = (int)e;
+    if (e == hipErrorOutOfMemory) fail(EVSL_ENOMEM);
+    fail(EVSL_EHIP);
+  }
+}
+#define HC(ctx, x) hipchk((ctx), (x))
+
+void *dalloc(evsl_ctx_t ctx, size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->last_hip = (int)e;
+    fail(EVSL_ENOMEM);
+  }
+  return p;
+}
+
+// Workspace slot `slot` of at least `bytes` bytes (contents not preserved on growth).
+void *ws(evsl_ctx_t ctx, int slot, size_t bytes) {
+  if ((int)ctx->ws_ptr.size() <= slot) {
+    ctx->ws_ptr.resize(slot + 1, nullptr);
+    ctx->ws_size.resize(slot + 1, 0);
+  }
+  if (ctx->ws_size[slot] < bytes) {
+    if (ctx->ws_ptr[slot]) {
+      HC(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipFree(ctx->ws_ptr[slot]);
+    }
+    ctx->ws_ptr[slot] = nullptr;
+    ctx->ws_size[slot] = 0;
+    ctx->ws_ptr[slot] = dalloc(ctx, bytes);
+    ctx->ws_size[slot] = bytes;
+  }
+  return ctx->ws_ptr[slot];
+}
+
+double *pinned(evsl_ctx_t ctx, size_t count) {
+  if (ctx->pinned_cap < count) {
+    if (ctx->pinned) {
+      HC(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipHostFree(ctx->pinned);
+      ctx->pinned = nullptr;
+      ctx->pinned_cap = 0;
+    }
+    void *p = nullptr;
+    HC(ctx, hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault));
+    ctx->pinned = (double *)p;
+    ctx->pinned_cap = count;
+  }
+  return ctx->pinned;
+}
+
+hipEvent_t get_event(evsl_ctx_t ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HC(ctx, hipEventCreate(&e));
+  return e;
+}
+
+// Resolve pending filter timings (waits for their completion).
+void resolve_pending(evsl_ctx_t ctx) {
+  for (auto &p : ctx->pending) {
+    HC(ctx, hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HC(ctx, hipEventElapsedTime(&ms, p.a, p.b));
+    ctx->filt_seconds += ms * 1e-3;
+    ctx->filt_launches += p.launches;
+    ctx->filt_bytes += p.bytes;
+    ctx->event_pool.push_back(p.a);
+    ctx->event_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+// Bracket a batch of filter launches with events (when timing is on).
+struct FilterTimer {
+  evsl_ctx_t ctx;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit FilterTimer(evsl_ctx_t c) : ctx(c) {
+    if (ctx->timing) {
+      a = get_event(ctx);
+      HC(ctx, hipEventRecord(a, ctx->stream));
+    }
+  }
+  void stop(int64_t launches, double bytes) {
+    if (ctx->timing) {
+      b = get_event(ctx);
+      HC(ctx, hipEventRecord(b, ctx->stream));
+      ctx->pending.push_back({a, b, launches, bytes});
+      if (ctx->pending.size() > 4096) resolve_pending(ctx);
+    } else {
+      ctx->filt_launches += launches;
+      ctx->filt_bytes += bytes;
+    }
+  }
+};
+
+evk::Csr to_csr(const evsl_csr_t *A) {
+  evk::Csr c;
+  c.n = (int)A->n;
+  c.nnz = A->nnz;
+  c.rp = A->row_ptr;
+  c.ci = A->col;
+  c.va = A->val;
+  c.dtype = A->dtype;
+  return c;
+}
+
+void check_csr(const evsl_csr_t *A) {
+  if (!A || A->n <= 0 || A->n >= (int64_t)1 << 31 || A->nnz < 0 || !A->row_ptr || !A->col ||
+      !A->val || (A->dtype != EVSL_F64 && A->dtype != EVSL_F32))
+    fail(EVSL_EINVAL);
+}
+
+// Algorithmic bytes of one filter step over nc columns (value size s):
+// the matrix once, plus P passes over the n x nc vectors.
+double step_bytes(const evsl_csr_t *A, int nc, int s, int passes) {
+  const double ma = (double)A->nnz * (s + 4) + 4.0 * (double)(A->n + 1);
+  return ma + (double)passes * (double)A->n * nc * s;
+}
+
+int pick_variant(evsl_ctx_t ctx) { return ctx->spmv_variant == 0 ? 2 : ctx->spmv_variant; }
+
+// --------------------------------------------------------------------------
+// Orthogonalisation helpers on a column-major basis B (n x *, leading dim ld).
+struct OrthWork {
+  double *partial;  // gemv_partials(n, ncap) doubles
+  double *h1, *h2;  // ncap
+  double *nrm2;     // 1 + ncol
+  double *scal;     // 4 per slot
+};
+
+// z <- z - B(B^T z), twice (classical Gram-Schmidt, second pass always made);
+// stores h1 + h2 into h1.
+void cgs2(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, OrthWork &w) {
+  if (nb <= 0) return;
+  evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h1);
+  evk::gemv_n_sub(s, n, nb, B, ld, w.h1, z);
+  evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h2);
+  evk::gemv_n_sub(s, n, nb, B, ld, w.h2, z);
+}
+
+__global__ void k_step_scalars(const double *h1, const double *h2, int idx, const double *nrm2,
+                               double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = idx >= 0 ? h1[idx] + h2[idx] : 0.0;
+    out[1] = sqrt(nrm2[0]);
+  }
+}
+
+}  // namespace
+
+// ==========================================================================
+// Slice solver: one slice of Algorithm alg:FiltLanTR driven step by step.
+namespace {
+
+struct Slice {
+  // problem
+  evsl_ctx_t ctx;
+  const evsl_csr_t *A;
+  int n;
+  double tlo, thi, lmin, lmax, normA, cc, dd, bar;
+  int deg;
+  std::vector<double> coef;
+  double *coef_dev = nullptr;
+  // options
+  int m, max_its, ncycle, nev_cap;
+  double tol;
+  uint64_t seed;
+  // device buffers
+  double *B = nullptr;  // n x cap_cols, column-major; locked columns first
+  int64_t ld = 0;
+  int cap_cols = 0;
+  double *z = nullptr, *w0 = nullptr, *w1 = nullptr;  // filter output and recurrence work
+  double *Uc = nullptr, *AUc = nullptr, *Yc = nullptr;
+  OrthWork ow{};
+  double *hostsc = nullptr;  // pinned: 2 scalars of the last step
+  // host state
+  std::vector<double> alpha, beta;  // alpha[i], beta[i] = coupling (i, i+1)
+  std::vector<double> th_tr, s_tr;  // thick-restart diagonal and arrow
+  std::vector<double> lam, res;     // locked pairs in lock order
+  int nlock = 0, l = 0, i = 0, its = 0, nmv = 0, nrand = 0, nocand = 0, nrestart = 0;
+  double t_old = NAN, t_new = NAN;
+  bool done = false;
+  int status = EVSL_OK;
+  bool next_ok = true;
+  double t_mv = 0, t_orth = 0, t_ritz = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+
+  Slice() = default;
+  Slice(const Slice &) = delete;
+  Slice &operator=(const Slice &) = delete;
+  ~Slice() { release(); }
+  void release() {
+    void *bufs[] = {coef_dev, B, z, w0, w1, Uc, AUc, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2,
+                    ow.scal};
+    for (void *p : bufs)
+      if (p) (void)hipFree(p);
+    coef_dev = B = z = w0 = w1 = Uc = AUc = Yc = nullptr;
+    ow = OrthWork{};
+    if (hostsc) (void)hipHostFree(hostsc);
+    hostsc = nullptr;
+    for (hipEvent_t *e : {&ev0, &ev1, &ev2})
+      if (*e) {
+        (void)hipEventDestroy(*e);
+        *e = nullptr;
+      }
+  }
+
+  hipStream_t st() const { return ctx->stream; }
+  double *col(int j) { return B + (int64_t)j * ld; }
+
+  void setup(evsl_ctx_t c, const evsl_csr_t *Am, const double intv[4], const evsl_pol_t *pol,
+             const evsl_lan_opts_t *opt) {
+    ctx = c;
+    A = Am;
+    n = (int)Am->n;
+    tlo = intv[0];
+    thi = intv[1];
+    lmin = intv[2];
+    lmax = intv[3];
+    normA = std::max(std::fabs(lmin), std::fabs(lmax));
+    if (!(thi > tlo) || !(lmax > lmin) || !pol || !pol->coef || pol->deg < 1) fail(EVSL_EINVAL);
+    cc = 0.5 * (lmax + lmin);
+    dd = 0.5 * (lmax - lmin);
+    if (std::fabs(pol->cc - cc) > 1e-12 * (1 + std::fabs(cc)) ||
+        std::fabs(pol->dd - dd) > 1e-12 * (1 + std::fabs(dd)))
+      fail(EVSL_EINVAL);
+    bar = pol->bar;
+    deg = pol->deg;
+    coef.assign(pol->coef, pol->coef + deg + 1);
+    const int nev_est = (opt && opt->nev_est > 0) ? opt->nev_est : 50;
+    m = (opt && opt->m > 0) ? opt->m : std::max(2 * nev_est + 30, 60);
+    if (m > n - 1) m = n - 1;
+    if (m < 2) fail(EVSL_EINVAL);
+    max_its = (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
+    ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : 30;
+    tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
+    seed = opt ? opt->seed : 0;
+    nev_cap = (opt && opt->nev_cap > 0) ? opt->nev_cap : std::max(2 * nev_est + 40, 100);
+    if (nev_cap > n) nev_cap = n;
+    if (opt && opt->prec == EVSL_F32) fail(EVSL_ENOTIMPL);
+    // device memory
+    ld = ((int64_t)n + 63) / 64 * 64;
+    cap_cols = nev_cap + m + 1;
+    B = (double *)dalloc(ctx, sizeof(double) * ld * cap_cols);
+    z = (double *)dalloc(ctx, sizeof(double) * ld);
+    w0 = (double *)dalloc(ctx, sizeof(double) * ld);
+    w1 = (double *)dalloc(ctx, sizeof(double) * ld);
+    Uc = (double *)dalloc(ctx, sizeof(double) * ld * m);
+    AUc = (double *)dalloc(ctx, sizeof(double) * ld * m);
+    Yc = (double *)dalloc(ctx, sizeof(double) * (size_t)m * m);
+    const int ncap = cap_cols + 8;
+    ow.partial = (double *)dalloc(
+        ctx, sizeof(double) * std::max(evk::gemv_partials(n, ncap), evk::dot_partials(n, m + 2)));
+    ow.h1 = (double *)dalloc(ctx, sizeof(double) * ncap);
+    ow.h2 = (double *)dalloc(ctx, sizeof(double) * ncap);
+    ow.nrm2 = (double *)dalloc(ctx, sizeof(double) * (3 * m + 8));
+    ow.scal = (double *)dalloc(ctx, sizeof(double) * 8);
+    coef_dev = (double *)dalloc(ctx, sizeof(double) * (deg + 1));
+    HC(ctx, hipMemcpyAsync(coef_dev, coef.data(), sizeof(double) * (deg + 1),
+                           hipMemcpyHostToDevice, st()));
+    void *hp = nullptr;
+    HC(ctx, hipHostMalloc(&hp, sizeof(double) * (3 * m + 8), hipHostMallocDefault));
+    hostsc = (double *)hp;
+    HC(ctx, hipEventCreate(&ev0));
+    HC(ctx, hipEventCreate(&ev1));
+    HC(ctx, hipEventCreate(&ev2));
+    alpha.assign(m + 1, 0.0);
+    beta.assign(m + 1, 0.0);
+    // q_1: seeded random unit vector
+    double nz = fresh_vector(0, col(0));
+    if (nz == 0.0) fail(EVSL_EINVAL);
+    l = 0;
+    i = 0;
+  }
+
+  // Random vector from restart block `nrand`, orthogonalised (twice) against
+  // the first nb columns of B and normalised into dst. Returns its norm after
+  // orthogonalisation relative to before (0 when it vanished). Synchronous.
+  double fresh_vector(int nb, double *dst) {
+    evk::lanczos_start(st(), n, seed, nrand++, z);
+    evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2 + 1);
+    cgs2(st(), n, nb, B, ld, z, ow);
+    cgs2(st(), n, nb, B, ld, z, ow);
+    evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
+    HC(ctx, hipMemcpyAsync(hostsc, ow.nrm2, 2 * sizeof(double), hipMemcpyDeviceToHost, st()));
+    HC(ctx, hipStreamSynchronize(st()));
+    const double after = std::sqrt(hostsc[0]), before = std::sqrt(hostsc[1]);
+    if (!(after > 1e-10 * before)) return 0.0;
+    evk::normalize(st(), n, z, dst, ow.nrm2, nullptr);
+    return after / before;
+  }
+
+  // --- one Lanczos step, split around the filter so that several slices can
+  // share one block filter launch.
+  const double *current() { return col(nlock + i); }
+
+  // Single-slice filter: z = rho(A-hat) q_i by the three-term recurrence.
+  void filter_single() {
+    const evk::Csr Ac = to_csr(A);
+    const int var = pick_variant(ctx);
+    const double *q = current();
+    FilterTimer tm(ctx);
+    HC(ctx, hipEventRecord(ev0, st()));
+    // W_1 = (A q - c q)/d; Y = c0 q + c1 W_1
+    evk::cheb_vec<double>(st(), Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z,
+                          ld, 1, coef_dev, deg + 1, 1);
+    // W_{j+1} is written over W_{j-1}; the input q itself is never written
+    const double *wprev = q;
+    double *wcur = w0;
+    for (int j = 1; j < deg; ++j) {
+      double *dst = (wprev == q) ? w1 : const_cast<double *>(wprev);
+      evk::cheb_vec<double>(st(), Ac, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
+                            dst, z, ld, 1, coef_dev, deg + 1, j + 1);
+      wprev = wcur;
+      wcur = dst;
+    }
+    HC(ctx, hipEventRecord(ev1, st()));
+    const double b0 = step_bytes(A, 1, 8, 3), b1 = step_bytes(A, 1, 8, 5);
+    tm.stop(deg, b0 + (deg - 1) * b1);
+    nmv += deg;
+  }
+
+  // Orthogonalise z against [locked, q_1..q_i], normalise into q_{i+1} and
+  // queue the two scalars (alpha_i, beta_{i+1}) for the host.
+  void orth_and_queue() {
+    const int nb = nlock + i + 1;
+    cgs2(st(), n, nb, B, ld, z, ow);
+    evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
+    evk::normalize(st(), n, z, col(nb), ow.nrm2, nullptr);
+    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, st(), ow.h1, ow.h2, nlock + i,
+                       ow.nrm2, ow.scal);
+    HC(ctx, hipEventRecord(ev2, st()));
+    HC(ctx, hipMemcpyAsync(hostsc, ow.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st()));
+  }
+
+  // Host part of the step (after the stream has been synchronised).
+  void after_step() {
+    float ms1 = 0.f, ms2 = 0.f;
+    if (hipEventElapsedTime(&ms1, ev0, ev1) == hipSuccess) t_mv += ms1 * 1e-3;
+    if (hipEventElapsedTime(&ms2, ev1, ev2) == hipSuccess) t_orth += ms2 * 1e-3;
+    its++;
+    const double a_i = hostsc[0], b_i = hostsc[1];
+    alpha[i] = a_i;
+    if (!std::isfinite(a_i) || !std::isfinite(b_i)) fail(EVSL_ESPECTRUM);
+    bool end_cycle = false;
+    next_ok = true;
+    if (b_i <= 1e-12) {
+      // invariant subspace of the filtered operator: new direction, coupling 0
+      double r = fresh_vector(nlock + i + 1, col(nlock + i + 1));
+      beta[i] = 0.0;
+      if (r == 0.0) {
+        next_ok = false;
+        end_cycle = true;
+      }
+    } else {
+      beta[i] = b_i;
+    }
+    if (!end_cycle && ((i + 1) - l) % ncycle == 0) {
+      const int k = i + 1;
+      std::vector<double> T = build_T(k), w(k);
+      evh::sym_eig(k, T.data(), w.data(), nullptr);
+      t_old = t_new;
+      t_new = 0.0;
+      for (double x : w)
+        if (x >= bar) t_new += x;
+      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new))) end_cycle = true;
+    }
+    if (its > max_its) end_cycle = true;
+    if (!end_cycle && i + 1 >= m) end_cycle = true;
+    if (end_cycle) {
+      const double t0 = now_s();
+      restart(i + 1);
+      t_ritz += now_s() - t0;
+      if (!done && its > max_its) {
+        status = EVSL_ENOCONV;
+        done = true;
+      }
+    } else {
+      i++;
+    }
+  }
+
+  // T of dimension k: thick-restart arrowhead block then tridiagonal.
+  std::vector<double> build_T(int k) {
+    std::vector<double> T((size_t)k * k, 0.0);
+    for (int j = 0; j < l && j < k; ++j) {
+      T[j + (size_t)j * k] = th_tr[j];
+      if (l < k) {
+        T[j + (size_t)l * k] = s_tr[j];
+        T[l + (size_t)j * k] = s_tr[j];
+      }
+    }
+    for (int r = l; r < k; ++r) {
+      T[r + (size_t)r * k] = alpha[r];
+      if (r + 1 < k) {
+        T[r + (size_t)(r + 1) * k] = beta[r];
+        T[(r + 1) + (size_t)r * k] = beta[r];
+      }
+    }
+    return T;
+  }
+
+  // Rayleigh-Ritz on T_dim, locking and thick restart.
+  void restart(int dim) {
+    nrestart++;
+    std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
+    evh::sym_eig(dim, T.data(), w.data(), Y.data());
+    const double beta_last = next_ok ? beta[dim - 1] : 0.0;
+    // candidates: Ritz values >= bar, largest first
+    std::vector<int> cand;
+    for (int j = dim - 1; j >= 0 && w[j] >= bar; --j) cand.push_back(j);
+    const int lc = (int)cand.size();
+    int naccept = 0;
+    std::vector<int> lock_sel, tr_sel;
+    std::vector<double> lock_lam, lock_res;
+    int cap_tr = m - std::max(ncycle, 10);
+    if (cap_tr < 1) cap_tr = 1;
+    if (lc > 0) {
+      std::vector<double> Yh((size_t)dim * lc);
+      for (int t = 0; t < lc; ++t)
+        std::copy(Y.begin() + (size_t)cand[t] * dim, Y.begin() + (size_t)cand[t] * dim + dim,
+                  Yh.begin() + (size_t)t * dim);
+      HC(ctx, hipMemcpyAsync(Yc, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice,
+                             st()));
+      // U_c = Q_dim Y_c ; A U_c ; Rayleigh quotients and residuals
+      evk::gemm_nn(st(), n, dim, lc, col(nlock), ld, Yc, dim, Uc, ld);
+      const evk::Csr Ac = to_csr(A);
+      evk::cheb_vec<double>(st(), Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, Uc, nullptr, AUc, nullptr, ld,
+                            lc, nullptr, 0, 0);
+      nmv += lc;
+      double *xx = ow.nrm2, *xax = ow.nrm2 + lc, *rr = ow.nrm2 + 2 * lc;
+      evk::col_dots(st(), n, lc, Uc, ld, Uc, ld, ow.partial, xx);
+      evk::col_dots(st(), n, lc, Uc, ld, AUc, ld, ow.partial, xax);
+      evk::col_resid2(st(), n, lc, Uc, AUc, ld, xax, xx, ow.partial, rr);
+      HC(ctx, hipMemcpyAsync(hostsc, ow.nrm2, sizeof(double) * 3 * lc, hipMemcpyDeviceToHost,
+                             st()));
+      HC(ctx, hipStreamSynchronize(st()));
+      for (int t = 0; t < lc; ++t) {
+        const double uu = hostsc[t], uau = hostsc[lc + t], r2 = hostsc[2 * lc + t];
+        const double lamt = uau / uu;
+        if (!std::isfinite(lamt)) fail(EVSL_ESPECTRUM);
+        if (lamt < tlo || lamt > thi) continue;  // outside the slice: ignored
+        naccept++;
+        const double r = std::sqrt(std::max(r2, 0.0) / uu) / normA;
+        if (r <= tol) {
+          lock_sel.push_back(t);
+          lock_lam.push_back(lamt);
+          lock_res.push_back(r);
+        } else if ((int)tr_sel.size() < cap_tr) {
+          tr_sel.push_back(t);
+        }
+      }
+      if (nlock + (int)lock_sel.size() > nev_cap) {
+        status = EVSL_ENOMEM;
+        done = true;
+        return;
+      }
+      // normalise the candidate vectors, then rebuild [locked | TR | q_next]
+      evk::normalize_cols(st(), n, lc, Uc, ld, xx);
+      if (next_ok)
+        HC(ctx, hipMemcpyAsync(z, col(nlock + dim), sizeof(double) * n, hipMemcpyDeviceToDevice,
+                               st()));
+      for (size_t q = 0; q < lock_sel.size(); ++q) {
+        HC(ctx, hipMemcpyAsync(col(nlock), Uc + (int64_t)lock_sel[q] * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st()));
+        lam.push_back(lock_lam[q]);
+        res.push_back(lock_res[q]);
+        nlock++;
+      }
+      th_tr.clear();
+      s_tr.clear();
+      for (size_t q = 0; q < tr_sel.size(); ++q) {
+        const int t = tr_sel[q];
+        HC(ctx, hipMemcpyAsync(col(nlock + (int)q), Uc + (int64_t)t * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st()));
+        th_tr.push_back(w[cand[t]]);
+        s_tr.push_back(beta_last * Y[(dim - 1) + (size_t)cand[t] * dim]);
+      }
+    }
+    if (naccept == 0) {
+      nocand++;
+      th_tr.clear();
+      s_tr.clear();
+      if (nocand >= 2) {
+        done = true;
+        return;
+      }
+      // extra restart: fresh random vector orthogonal to the locked set
+      l = 0;
+      if (fresh_vector(nlock, col(nlock)) == 0.0) done = true;
+    } else {
+      nocand = 0;
+      l = (int)tr_sel.size();
+      if (next_ok) {
+        HC(ctx, hipMemcpyAsync(col(nlock + l), z, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                               st()));
+      } else {
+        if (fresh_vector(nlock + l, col(nlock + l)) == 0.0) {
+          done = true;
+          return;
+        }
+        std::fill(s_tr.begin(), s_tr.end(), 0.0);
+      }
+    }
+    std::fill(alpha.begin(), alpha.end(), 0.0);
+    std::fill(beta.begin(), beta.end(), 0.0);
+    i = l;
+    t_old = t_new = NAN;
+    if (nlock + m + 1 > cap_cols) {
+      status = EVSL_ENOMEM;
+      done = true;
+    }
+  }
+
+  // Copy the locked pairs, sorted by eigenvalue, into a result.
+  void emit(evsl_eigs_t *out) {
+    HC(ctx, hipStreamSynchronize(st()));
+    const int k = nlock;
+    std::vector<int> idx(k);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    out->nev = k;
+    out->lam = (double *)std::malloc(sizeof(double) * std::max(k, 1));
+    out->res = (double *)std::malloc(sizeof(double) * std::max(k, 1));
+    if (!out->lam || !out->res) fail(EVSL_ENOMEM);
+    out->Y = nullptr;
+    if (k > 0) out->Y = (double *)dalloc(ctx, sizeof(double) * (size_t)n * k);
+    for (int j = 0; j < k; ++j) {
+      out->lam[j] = lam[idx[j]];
+      out->res[j] = res[idx[j]];
+      HC(ctx, hipMemcpyAsync(out->Y + (int64_t)j * n, col(idx[j]), sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, st()));
+    }
+    HC(ctx, hipStreamSynchronize(st()));
+    out->niter = its;
+    out->nmv = nmv;
+    out->nrestart = nrestart;
+    out->status = status == EVSL_ENOMEM ? EVSL_ENOCONV : status;
+    out->t_mv = t_mv;
+    out->t_orth = t_orth;
+    out->t_ritz = t_ritz;
+  }
+};
+
+}  // namespace
+
+// ==========================================================================
+// C-ABI
+extern "C" {
+
+const char *evsl_strerror(int code) {
+  switch (code) {
+    case EVSL_OK: return "ok";
+    case EVSL_EINVAL: return "invalid argument";
+    case EVSL_ENOMEM: return "out of memory";
+    case EVSL_EHIP: return "HIP runtime error";
+    case EVSL_EDEGREE: return "filter degree reached max_deg";
+    case EVSL_ENOCONV: return "not converged within max_its";
+    case EVSL_ESPECTRUM: return "filter blow-up: spectrum bounds do not contain the spectrum";
+    case EVSL_ENOTIMPL: return "not implemented";
+    default: return "unknown error";
+  }
+}
+
+#define EVSL_GUARD_BEGIN try {
+#define EVSL_GUARD_END                \
+  }                                   \
+  catch (const Error &e) {            \
+    return e.code;                    \
+  }                                   \
+  catch (const std::bad_alloc &) {    \
+    return EVSL_ENOMEM;               \
+  }                                   \
+  catch (...) {                       \
+    return EVSL_EINVAL;               \
+  }
+
+int evsl_create(evsl_ctx_t *ctx, void *stream) {
+  if (!ctx) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  evsl_ctx_s *c = new evsl_ctx_s();
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return EVSL_EHIP;
+  }
+  *ctx = c;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_destroy(evsl_ctx_t ctx) {
+  if (!ctx) return EVSL_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (void *p : ctx->ws_ptr)
+    if (p) (void)hipFree(p);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return EVSL_OK;
+}
+
+int evsl_last_hip_error(evsl_ctx_t ctx) { return ctx ? ctx->last_hip : 0; }
+
+int evsl_set_timing(evsl_ctx_t ctx, int on) {
+  if (!ctx) return EVSL_EINVAL;
+  ctx->timing = on != 0;
+  return EVSL_OK;
+}
+
+int evsl_set_spmv_variant(evsl_ctx_t ctx, int variant) {
+  if (!ctx || variant < 0 || variant > 2) return EVSL_EINVAL;
+  ctx->spmv_variant = variant;
+  return EVSL_OK;
+}
+
+int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes) {
+  if (!ctx) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  resolve_pending(ctx);
+  if (launches) *launches = ctx->filt_launches;
+  if (seconds) *seconds = ctx->filt_seconds;
+  if (bytes) *bytes = ctx->filt_bytes;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_reset_stats(evsl_ctx_t ctx) {
+  if (!ctx) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  resolve_pending(ctx);
+  ctx->filt_launches = 0;
+  ctx->filt_seconds = 0.0;
+  ctx->filt_bytes = 0.0;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_cheb_coeffs(const double intv[4], int damping, double tau, double tau_ext, int max_deg,
+                     evsl_pol_t *pol) {
+  if (!intv || !pol || !pol->coef || max_deg < 2 || pol->cap < max_deg + 1 || damping < 0 ||
+      damping > 2)
+    return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  evh::FilterOut fo{};
+  fo.coef = pol->coef;
+  const int rc = evh::find_filter(intv, damping, tau, tau_ext, max_deg, &fo);
+  if (rc < 0) return EVSL_EINVAL;
+  pol->deg = fo.deg;
+  pol->boundary = fo.boundary;
+  pol->gamma = fo.gamma;
+  pol->cc = fo.cc;
+  pol->dd = fo.dd;
+  pol->bar = fo.bar;
+  return rc == 1 ? EVSL_EDEGREE : EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_kpm_count(const double *moments, int degree, int damping, double lmin, double lmax,
+                   double x0, double x1, double *count) {
+  if (!moments || !count || degree < 0 || !(lmax > lmin)) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  std::vector<double> g(degree + 1);
+  if (evh::damping_factors(damping, degree, g.data()) != 0) return EVSL_EINVAL;
+  *count = evh::kpm_count(degree, moments, g.data(), 0.5 * (lmax + lmin), 0.5 * (lmax - lmin), x0,
+                          x1);
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_slice_spectrum(const double *moments, int degree, int damping, const double intv[4],
+                        int nslices, int npts, double *sli) {
+  if (!moments || !intv || !sli || degree < 0) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  return evh::slice(degree, moments, damping, intv, nslices, npts, sli) == 0 ? EVSL_OK
+                                                                             : EVSL_EINVAL;
+  EVSL_GUARD_END
+}
+
+int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int degree, int nvec,
+                 uint64_t seed, int damping, double *moments, double *nev_est) {
+  if (!ctx || !intv || !moments || degree < 1 || nvec < 1 || damping < 0 || damping > 2)
+    return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  if (!(intv[3] > intv[2])) return EVSL_EINVAL;
+  const int n = (int)A->n;
+  const double c = 0.5 * (intv[3] + intv[2]), d = 0.5 * (intv[3] - intv[2]);
+  const size_t blk = (size_t)n * nvec;
+  double *V = (double *)ws(ctx, 0, sizeof(double) * blk);
+  double *Wa = (double *)ws(ctx, 1, sizeof(double) * blk);
+  double *Wb = (double *)ws(ctx, 2, sizeof(double) * blk);
+  const int nw = evk::blk_partials(n, nvec);
+  const int nwd = evk::dot_partials((int)std::min<size_t>(blk, 0x7fffffff), 1);
+  double *part = (double *)ws(ctx, 3, sizeof(double) * ((size_t)nw * (degree + 1) + nwd + 8));
+  double *mom_dev = (double *)ws(ctx, 4, sizeof(double) * (degree + 2));
+  hipStream_t s = ctx->stream;
+  const evk::Csr Ac = to_csr(A);
+  evk::rademacher(s, n, nvec, seed, V);
+  // zeta_0 = (1/nvec) V . V
+  evk::col_dots(s, (int)blk, 1, V, 0, V, 0, part + (size_t)nw * (degree + 1), mom_dev);
+  FilterTimer tm(ctx);
+  // T_1(A-hat) V and its dot with V
+  evk::cheb_blk<double>(s, Ac, evk::STEP_KPM_FIRST, 1.0 / d, -c / d, V, nullptr, Wa, nullptr, nvec,
+                        nvec, nullptr, 0, 0, V, part + (size_t)nw * 1);
+  // T_{k} is written over T_{k-2}; the probe block V itself is never written
+  const double *wprev = V;
+  double *wcur = Wa;
+  for (int k = 2; k <= degree; ++k) {
+    double *dst = (wprev == V) ? Wb : const_cast<double *>(wprev);
+    evk::cheb_blk<double>(s, Ac, evk::STEP_KPM_NEXT, 2.0 / d, -2.0 * c / d, wcur, wprev, dst,
+                          nullptr, nvec, nvec, nullptr, 0, 0, V, part + (size_t)nw * k);
+    wprev = wcur;
+    wcur = dst;
+  }
+  tm.stop(degree, step_bytes(A, nvec, 8, 3) + (degree - 1) * step_bytes(A, nvec, 8, 4));
+  evk::reduce_partials(s, nw, degree, part + nw, 1.0 / nvec, mom_dev + 1);
+  HC(ctx, hipMemcpyAsync(moments, mom_dev, sizeof(double) * (degree + 1), hipMemcpyDeviceToHost,
+                         s));
+  HC(ctx, hipStreamSynchronize(s));
+  moments[0] /= nvec;
+  if (nev_est) {
+    std::vector<double> g(degree + 1);
+    evh::damping_factors(damping, degree, g.data());
+    *nev_est = evh::kpm_count(degree, moments, g.data(), c, d, intv[0], intv[1]);
+  }
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64_t seed,
+                         double *lmin, double *lmax) {
+  if (!ctx || !lmin || !lmax || nsteps < 1) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const int n = (int)A->n;
+  const int m = (int)std::min<int64_t>(nsteps, n);
+  const int64_t ld = ((int64_t)n + 63) / 64 * 64;
+  hipStream_t s = ctx->stream;
+  double *Q = (double *)ws(ctx, 0, sizeof(double) * ld * (m + 1));
+  double *z = (double *)ws(ctx, 1, sizeof(double) * ld);
+  OrthWork ow;
+  ow.partial = (double *)ws(ctx, 2, sizeof(double) * std::max(evk::gemv_partials(n, m + 2),
+                                                             evk::dot_partials(n, 2)));
+  ow.h1 = (double *)ws(ctx, 3, sizeof(double) * (m + 2));
+  ow.h2 = (double *)ws(ctx, 4, sizeof(double) * (m + 2));
+  ow.nrm2 = (double *)ws(ctx, 5, sizeof(double) * 8);
+  ow.scal = (double *)ws(ctx, 6, sizeof(double) * (2 * m + 8));
+  double *hs = pinned(ctx, 2 * m + 8);
+  const evk::Csr Ac = to_csr(A);
+  evk::lanczos_start(s, n, seed, 0, z);
+  evk::col_dots(s, n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
+  evk::normalize(s, n, z, Q, ow.nrm2, nullptr);
+  int dim = m;
+  for (int i = 0; i < m; ++i) {
+    evk::cheb_vec<double>(s, Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, Q + (int64_t)i * ld, nullptr, z,
+                          nullptr, ld, 1, nullptr, 0, 0);
+    cgs2(s, n, i + 1, Q, ld, z, ow);
+    evk::col_dots(s, n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
+    evk::normalize(s, n, z, Q + (int64_t)(i + 1) * ld, ow.nrm2, nullptr);
+    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, s, ow.h1, ow.h2, i, ow.nrm2,
+                       ow.scal + 2 * i);
+    HC(ctx, hipMemcpyAsync(hs + 2 * i, ow.scal + 2 * i, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+    if ((i & 15) == 15 || i == m - 1) {
+      HC(ctx, hipStreamSynchronize(s));
+      // stop at an invariant subspace
+      bool stop = false;
+      double scale = 0.0;
+      for (int t = 0; t <= i; ++t) {
+        scale = std::max(scale, std::fabs(hs[2 * t]) + (t > 0 ? hs[2 * t - 1] : 0.0));
+        if (hs[2 * t + 1] <= 1e-12 * scale) {
+          dim = t + 1;
+          stop = true;
+          break;
+        }
+      }
+      if (stop) break;
+    }
+  }
+  HC(ctx, hipStreamSynchronize(s));
+  std::vector<double> T((size_t)dim * dim, 0.0), w(dim), Y((size_t)dim * dim);
+  for (int t = 0; t < dim; ++t) {
+    T[t + (size_t)t * dim] = hs[2 * t];
+    if (t + 1 < dim) {
+      T[t + (size_t)(t + 1) * dim] = hs[2 * t + 1];
+      T[(t + 1) + (size_t)t * dim] = hs[2 * t + 1];
+    }
+  }
+  evh::sym_eig(dim, T.data(), w.data(), Y.data());
+  const double blast = hs[2 * (dim - 1) + 1];
+  *lmin = w[0] - std::fabs(blast * Y[(dim - 1) + 0]);
+  *lmax = w[dim - 1] + std::fabs(blast * Y[(dim - 1) + (size_t)(dim - 1) * dim]);
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
+                      const int32_t *col_group, const void *V, void *Y, int64_t ldv, int ncols,
+                      int prec) {
+  if (!ctx || !pols || npol < 1 || !col_group || !V || !Y || ncols < 1 || ldv < ncols ||
+      (prec != EVSL_F64 && prec != EVSL_F32))
+    return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if ((prec == EVSL_F32) != (A->dtype == EVSL_F32)) return EVSL_EINVAL;
+  const int n = (int)A->n;
+  int kmax = 0;
+  for (int c = 0; c < ncols; ++c) {
+    const int g = col_group[c];
+    if (g < 0 || g >= npol) return EVSL_EINVAL;
+    const evsl_pol_t &p = pols[g];
+    if (!p.coef || p.deg < 1) return EVSL_EINVAL;
+    if (std::fabs(p.cc - pols[0].cc) > 1e-13 * (1 + std::fabs(p.cc)) ||
+        std::fabs(p.dd - pols[0].dd) > 1e-13 * (1 + std::fabs(p.dd)))
+      return EVSL_EINVAL;
+    kmax = std::max(kmax, p.deg);
+  }
+  const double c0 = pols[0].cc, d0 = pols[0].dd;
+  // per-column coefficient table (zero beyond each column's degree) and the
+  // number of columns still active at each step when degrees do not increase
+  const int cld = kmax + 1;
+  std::vector<double> tab((size_t)ncols * cld, 0.0);
+  bool sorted = true;
+  for (int c = 0; c < ncols; ++c) {
+    const evsl_pol_t &p = pols[col_group[c]];
+    std::copy(p.coef, p.coef + p.deg + 1, tab.begin() + (size_t)c * cld);
+    if (c > 0 && p.deg > pols[col_group[c - 1]].deg) sorted = false;
+  }
+  std::vector<int> active(kmax + 1, ncols);
+  if (sorted)
+    for (int j = 0; j <= kmax; ++j) {
+      int a = 0;
+      while (a < ncols && pols[col_group[a]].deg >= j) ++a;
+      active[j] = std::max(a, 1);
+    }
+  hipStream_t s = ctx->stream;
+  double *ctab = (double *)ws(ctx, 10, sizeof(double) * tab.size());
+  HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+  // the table lives on this frame: wait for the upload before returning
+  HC(ctx, hipStreamSynchronize(s));
+  const size_t es = prec == EVSL_F64 ? 8 : 4;
+  void *Wa = ws(ctx, 11, es * (size_t)n * ldv);
+  void *Wb = ws(ctx, 12, es * (size_t)n * ldv);
+  const evk::Csr Ac = to_csr(A);
+  FilterTimer tm(ctx);
+  double bytes = 0.0;
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const T *v = (const T *)V;
+    T *y = (T *)Y, *wa = (T *)Wa, *wb = (T *)Wb;
+    const bool vec = (ncols == 1 && ldv == 1);
+    if (vec) {
+      const int var = pick_variant(ctx);
+      evk::cheb_vec<T>(s, Ac, var, evk::STEP_FIRST, 1.0 / d0, -c0 / d0, v, nullptr, wa, y, n, 1,
+                       ctab, cld, 1);
+    } else {
+      evk::cheb_blk<T>(s, Ac, evk::STEP_FIRST, 1.0 / d0, -c0 / d0, v, nullptr, wa, y, ldv,
+                       active[1], ctab, cld, 1, nullptr, nullptr);
+    }
+    bytes += step_bytes(A, active[1], (int)es, 3);
+    // W_{j+1} is written over W_{j-1}; V itself is never written
+    const T *wprev = v;
+    T *wcur = wa;
+    for (int j = 1; j < kmax; ++j) {
+      const int nc = active[j + 1];
+      T *dst = (wprev == v) ? wb : const_cast<T *>(wprev);
+      if (vec) {
+        const int var = pick_variant(ctx);
+        evk::cheb_vec<T>(s, Ac, var, evk::STEP_NEXT, 2.0 / d0, -2.0 * c0 / d0, wcur, wprev, dst,
+                         y, n, 1, ctab, cld, j + 1);
+      } else {
+        evk::cheb_blk<T>(s, Ac, evk::STEP_NEXT, 2.0 / d0, -2.0 * c0 / d0, wcur, wprev, dst, y,
+                         ldv, nc, ctab, cld, j + 1, nullptr, nullptr);
+      }
+      bytes += step_bytes(A, nc, (int)es, 5);
+      wprev = wcur;
+      wcur = dst;
+    }
+  };
+  if (prec == EVSL_F64)
+    run(double());
+  else
+    run(float());
+  tm.stop(kmax, bytes);
+  if (hipGetLastError() != hipSuccess) return EVSL_EHIP;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4],
+                          const evsl_pol_t *pol, const evsl_lan_opts_t *opt, evsl_eigs_t *out) {
+  if (!ctx || !intv || !pol || !out) return EVSL_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const double t0 = now_s();
+  Slice sl;
+  sl.setup(ctx, A, intv, pol, opt);
+  while (!sl.done) {
+    sl.filter_single();
+    sl.orth_and_queue();
+    HC(ctx, hipStreamSynchronize(ctx->stream));
+    sl.after_step();
+  }
+  sl.emit(out);
+  out->t_tot = now_s() - t0;
+  return out->status;
+  EVSL_GUARD_END
+}
+
+int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices,
+                                const double *intv, const evsl_pol_t *pols,
+                                const evsl_lan_opts_t *opts, evsl_eigs_t *outs) {
+  if (!ctx || nslices < 1 || !intv || !pols || !outs) return EVSL_EINVAL;
+  for (int q = 0; q < nslices; ++q) std::memset(&outs[q], 0, sizeof(outs[q]));
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const double t0 = now_s();
+  const int n = (int)A->n;
+  std::vector<Slice> sl(nslices);
+  for (int q = 0; q < nslices; ++q)
+    sl[q].setup(ctx, A, intv + 4 * q, &pols[q], opts ? &opts[q] : nullptr);
+  const double cc = sl[0].cc, dd = sl[0].dd;
+  for (int q = 1; q < nslices; ++q)
+    if (std::fabs(sl[q].cc - cc) > 1e-13 * (1 + std::fabs(cc)) ||
+        std::fabs(sl[q].dd - dd) > 1e-13 * (1 + std::fabs(dd)))
+      return EVSL_EINVAL;
+  // slices ordered by degree (non-increasing) so that the active columns of
+  // the block recurrence form a prefix that shrinks as low degrees finish
+  std::vector<int> order(nslices);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sl[a].deg > sl[b].deg; });
+  int kmax = 0;
+  for (auto &s : sl) kmax = std::max(kmax, s.deg);
+  hipStream_t s = ctx->stream;
+  double *X0 = (double *)ws(ctx, 20, sizeof(double) * (size_t)n * nslices);
+  double *X1 = (double *)ws(ctx, 21, sizeof(double) * (size_t)n * nslices);
+  double *Yb = (double *)ws(ctx, 22, sizeof(double) * (size_t)n * nslices);
+  double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)nslices * (kmax + 1));
+  double **ptrs = (double **)ws(ctx, 24, sizeof(double *) * 2 * nslices);
+  const evk::Csr Ac = to_csr(A);
+  std::vector<int> act, prev_act;
+  std::vector<double> tab;
+  std::vector<int> ncs(kmax + 2);
+  while (true) {
+    act.clear();
+    for (int q : order)
+      if (!sl[q].done) act.push_back(q);
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    int km = 0;
+    for (int q : act) km = std::max(km, sl[q].deg);
+    if (act != prev_act) {
+      tab.assign((size_t)na * (km + 1), 0.0);
+      for (int c = 0; c < na; ++c)
+        std::copy(sl[act[c]].coef.begin(), sl[act[c]].coef.end(), tab.begin() + (size_t)c * (km + 1));
+      HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
+                             s));
+      for (int j = 0; j <= km; ++j) {
+        int a = 0;
+        while (a < na && sl[act[a]].deg >= j) ++a;
+        ncs[j] = std::max(a, 1);
+      }
+      prev_act = act;
+    }
+    // gather the current Lanczos vectors of the active slices, filter them
+    // together, scatter the results
+    std::vector<const double *> src(na);
+    std::vector<double *> dst(na);
+    for (int c = 0; c < na; ++c) {
+      src[c] = sl[act[c]].current();
+      dst[c] = sl[act[c]].z;
+    }
+    HC(ctx, hipMemcpyAsync(ptrs, src.data(), sizeof(double *) * na, hipMemcpyHostToDevice, s));
+    HC(ctx, hipMemcpyAsync(ptrs + nslices, dst.data(), sizeof(double *) * na,
+                           hipMemcpyHostToDevice, s));
+    evk::gather_cols(s, n, na, (const double *const *)ptrs, X0, na);
+    FilterTimer tm(ctx);
+    for (int q : act) HC(ctx, hipEventRecord(sl[q].ev0, s));
+    double bytes = 0.0;
+    evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, na,
+                          ncs[1], ctab, km + 1, 1, nullptr, nullptr);
+    bytes += step_bytes(A, ncs[1], 8, 3);
+    // X0 = W_0, X1 = W_1; W_{j+1} is written over W_{j-1}
+    double *wprev = X0, *wcur = X1;
+    for (int j = 1; j < km; ++j) {
+      evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
+                            Yb, na, ncs[j + 1], ctab, km + 1, j + 1, nullptr, nullptr);
+      bytes += step_bytes(A, ncs[j + 1], 8, 5);
+      std::swap(wprev, wcur);
+    }
+    for (int q : act) HC(ctx, hipEventRecord(sl[q].ev1, s));
+    tm.stop(km, bytes);
+    evk::scatter_cols(s, n, na, Yb, na, (double *const *)(ptrs + nslices));
+    for (int q : act) {
+      sl[q].nmv += sl[q].deg;
+      sl[q].orth_and_queue();
+    }
+    HC(ctx, hipStreamSynchronize(s));
+    for (int q : act) sl[q].after_step();
+  }
+  int rc = EVSL_OK;
+  for (int q = 0; q < nslices; ++q) {
+    sl[q].emit(&outs[q]);
+    outs[q].t_tot = now_s() - t0;
+    if (outs[q].status != EVSL_OK) rc = outs[q].status;
+  }
+  return rc;
+  EVSL_GUARD_END
+}
+
+int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, double *dst,
+                          int64_t ldd) {
+  if (!ctx || !out || !dst || n <= 0 || ldd < n || (out->nev > 0 && !out->Y)) return EVSL_EINVAL;
+  if (out->nev == 0) return EVSL_OK;
+  hipError_t e = hipMemcpy2DAsync(dst, ldd * sizeof(double), out->Y, n * sizeof(double),
+                                  n * sizeof(double), out->nev, hipMemcpyDeviceToDevice,
+                                  ctx->stream);
+  if (e != hipSuccess) {
+    ctx->last_hip = (int)e;
+    return EVSL_EHIP;
+  }
+  return EVSL_OK;
+}
+
+void evsl_eigs_free(evsl_ctx_t ctx, evsl_eigs_t *out) {
+  (void)ctx;
+  if (!out) return;
+  std::free(out->lam);
+  std::free(out->res);
+  if (out->Y) (void)hipFree(out->Y);
+  out->lam = out->res = out->Y = nullptr;
+  out->nev = 0;
+}
+
+}  // extern "C"

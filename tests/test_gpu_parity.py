@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs, and against closed forms at full size.
+
+Tolerances (FP64):
+* filter p(A-hat)V: ||Y_gpu - Y_oracle|| / ||V|| <= 1e-11 max(1, k/2000). Both
+  sides run the forward three-term recurrence, whose rounding error grows
+  O(k eps) on [-1, 1]; only the summation order differs.
+* KPM moments: 1e-12 relative to n (the moments are O(n) sums).
+* eigenvalues: |dlambda| <= 1e-10 max(|lambda|, 1e-6 ||A||); residuals <= tol;
+  eigenvectors checked by residual and orthogonality, never elementwise.
+"""
+import numpy as np
+import pytest
+
+import evsl_inputs as I
+import oracle
+import paper_1802_05215_amd as ev
+from tests.closed_form import lap_eig_of, lap_eigs, lap_eigvec
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    ev.load()
+    c = ev.Ctx()
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _pol(intv, damp=ev.DAMP_JACKSON):
+    return ev.evsl_cheb_coeffs(intv, damping=damp, tau=0.8, tau_ext=0.4)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("N,dim,pot,intv", [(40, 2, None, [1.0, 1.6, 0.0, 8.0]),
+                                            (13, 3, 0, [2.0, 2.3, 0.0, 13.0]),
+                                            (23, 2, 5, [0.0, 0.7, 0.0, 9.0])])
+def test_filter_single_vector_matches_oracle(ctx, variant, N, dim, pot, intv):
+    A = I.laplacian(N, dim, pot_seed=pot)
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol(intv)
+    v = I.lanczos_start(9, A.n)
+    ctx.set_spmv_variant(variant)
+    V = _dev(v)
+    Y = torch.empty_like(V)
+    ev.evsl_filter_apply(ctx, Ad, [p], [0], V, Y)
+    torch.cuda.synchronize()
+    ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, v)
+    err = np.linalg.norm(Y.cpu().numpy() - ref) / np.linalg.norm(v)
+    assert err <= 1e-11 * max(1.0, p.deg / 2000), (err, p.deg)
+    ctx.set_spmv_variant(0)
+
+
+@pytest.mark.parametrize("sorted_cols", [True, False])
+def test_filter_block_matches_oracle(ctx, sorted_cols):
+    A = I.laplacian(37, 2, pot_seed=1)             # n = 1369: ragged against every tile
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = 0.0, 9.0
+    pols = [_pol([a, b, lo, hi]) for a, b in [(1.0, 1.3), (2.0, 2.1), (0.0, 0.9)]]
+    groups = [1, 1, 0, 0, 2] if sorted_cols else [0, 2, 1, 0, 1]
+    degs = [pols[g].deg for g in groups]
+    if sorted_cols:
+        assert all(degs[i] >= degs[i + 1] for i in range(len(degs) - 1))
+    ncols, ld = 5, 8
+    rng = np.random.default_rng(4)
+    Vh = np.zeros((A.n, ld))
+    Vh[:, :ncols] = rng.standard_normal((A.n, ncols))
+    V = _dev(Vh)
+    Y = torch.zeros_like(V)
+    ev.evsl_filter_apply(ctx, Ad, pols, groups, V[:, :ncols], Y[:, :ncols])
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy()
+    for c in range(ncols):
+        p = pols[groups[c]]
+        ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, Vh[:, c])
+        err = np.linalg.norm(Yh[:, c] - ref) / np.linalg.norm(Vh[:, c])
+        assert err <= 1e-11, (c, err)
+    assert np.all(Yh[:, ncols:] == 0.0)           # padding columns untouched
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_filter_closed_form_eigenvector_full_size(ctx, variant):
+    # 100^3 Laplacian (n = 1e6, the plain-method matrix without its potential)
+    N = 100
+    A = I.laplacian(N, 3)
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol([0.60, 0.61, 0.0, 12.0])
+    ctx.set_spmv_variant(variant)
+    for modes in ((1, 1, 1), (11, 17, 3), (60, 2, 41)):
+        u = lap_eigvec(N, 3, modes)
+        lam = lap_eig_of(N, modes)
+        rho = np.polynomial.chebyshev.chebval((lam - p.cc) / p.dd, p.coef)
+        U = _dev(u)
+        Y = torch.empty_like(U)
+        ev.evsl_filter_apply(ctx, Ad, [p], [0], U, Y)
+        torch.cuda.synchronize()
+        err = np.linalg.norm(Y.cpu().numpy() - rho * u) / np.linalg.norm(u)
+        assert err <= 1e-11 * max(1.0, p.deg / 2000), (modes, err, p.deg)
+    ctx.set_spmv_variant(0)
+
+
+def test_filter_is_deterministic(ctx):
+    A = I.laplacian(30, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol([0.6, 0.7, 0.0, 13.0])
+    V = _dev(I.lanczos_start(1, A.n))
+    Y1, Y2 = torch.empty_like(V), torch.empty_like(V)
+    ev.evsl_filter_apply(ctx, Ad, [p], [0], V, Y1)
+    ev.evsl_filter_apply(ctx, Ad, [p], [0], V, Y2)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+
+
+@pytest.mark.parametrize("N,dim,pot,K,nv", [(40, 2, None, 40, 10), (17, 3, 0, 80, 20)])
+def test_kpm_moments_match_oracle(ctx, N, dim, pot, K, nv):
+    A = I.laplacian(N, dim, pot_seed=pot)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    intv = [1.0, 1.6, lo, hi]
+    mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, K, nv, seed=1, damping=ev.DAMP_JACKSON)
+    V = oracle.rademacher(1, A.n, nv)
+    ref = oracle.kpm_moments(A, lo, hi, K, V)
+    assert np.abs(mom - ref).max() <= 1e-12 * A.n
+    cnt = oracle.kpm_count(ref, oracle.DAMP_JACKSON, lo, hi, 1.0, 1.6)
+    assert abs(est - cnt) <= 1e-9 * max(1.0, cnt)
+
+
+@pytest.mark.parametrize("N,dim,pot", [(40, 2, None), (20, 3, 0), (60, 3, 0)])
+def test_bounds_match_oracle_and_contain_spectrum(ctx, N, dim, pot):
+    A = I.laplacian(N, dim, pot_seed=pot)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    rlo, rhi = oracle.lanczos_bounds(A, 80, 3)
+    assert abs(lo - rlo) <= 1e-8 and abs(hi - rhi) <= 1e-8
+    if pot is None:
+        ex = lap_eigs(N, dim)
+        elo, ehi = ex[0], ex[-1]
+    elif A.n <= 8000:
+        w = np.linalg.eigvalsh(A.to_dense())
+        elo, ehi = w[0], w[-1]
+    else:
+        # Rayleigh quotients of the extreme sine modes bound the extreme eigenvalues
+        u = lap_eigvec(N, dim, (1,) * dim)
+        v = lap_eigvec(N, dim, (N,) * dim)
+        elo = u @ oracle.spmv(A, u) / (u @ u)
+        ehi = v @ oracle.spmv(A, v) / (v @ v)
+    assert lo <= elo + 1e-12 and hi >= ehi - 1e-12
+
+
+def _closed_form_interval(N, dim, a, b):
+    ex = lap_eigs(N, dim)
+    return ex[(ex >= a) & (ex <= b)]
+
+
+def test_filtered_lanczos_40x40_all_91(ctx):
+    """2-D 5-point Laplacian on 40 x 40, [1.0, 1.6]: 91 eigenvalues, 88 of them in
+    exact double pairs, residual <= 1e-10."""
+    A = I.laplacian(40, 2)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.6, lo, hi]
+    mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 40, 10, seed=1, damping=ev.DAMP_JACKSON)
+    p = _pol(intv)
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, intv, p,
+                                               ev.lan_opts(tol=1e-10, seed=2, nev_est=int(est)))
+    want = _closed_form_interval(40, 2, 1.0, 1.6)
+    assert len(want) == 91 and st["nev"] == 91 and st["status"] == 0
+    assert np.abs(lam - want).max() <= 1e-10 * np.abs(want).max()
+    assert res.max() <= 1e-10
+    Yh = Y.cpu().numpy()
+    assert np.abs(Yh.T @ Yh - np.eye(91)).max() <= 1e-12
+    # the oracle on the same inputs finds the same list
+    olam, _, ores, _ = oracle.filtered_lanczos(A, intv, oracle.find_pol(intv, damping=2),
+                                               tol=1e-10, nev_est=int(est))
+    assert len(olam) == 91 and np.abs(olam - lam).max() <= 1e-10 * 8
+
+
+def test_filtered_lanczos_potential_matches_dense(ctx):
+    A = I.laplacian(20, 2, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [2.0, 2.6, lo, hi]
+    w = np.linalg.eigvalsh(A.to_dense())
+    want = w[(w >= 2.0) & (w <= 2.6)]
+    p = _pol(intv)
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, intv, p,
+                                               ev.lan_opts(tol=1e-10, nev_est=len(want)))
+    assert len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-10 * np.abs(want).max()
+    R = A.to_dense() @ Y.cpu().numpy() - Y.cpu().numpy() * lam
+    assert np.linalg.norm(R, axis=0).max() <= 1e-10 * max(abs(lo), abs(hi))
+    olam, _, _, _ = oracle.filtered_lanczos(A, intv, oracle.find_pol(intv, damping=2), tol=1e-10,
+                                            nev_est=len(want))
+    assert np.abs(olam - lam).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_filtered_lanczos_boundary_slice_triples(ctx):
+    N = 10
+    A = I.laplacian(N, 3)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [lo, 1.4, lo, hi]
+    p = _pol(intv)
+    assert p.boundary == -1
+    want = _closed_form_interval(N, 3, -1.0, 1.4)
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, intv, p,
+                                               ev.lan_opts(tol=1e-10, nev_est=len(want)))
+    assert len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-10 * 12
+
+
+def test_filtered_lanczos_empty_slice(ctx):
+    A = I.laplacian(12, 2)
+    Ad = ev.DeviceCsr.from_host(A)
+    u = np.unique(np.round(lap_eigs(12, 2), 12))
+    i = np.argmax(np.diff(u[10:50])) + 10
+    a, b = u[i] + 0.2 * (u[i + 1] - u[i]), u[i + 1] - 0.2 * (u[i + 1] - u[i])
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, [a, b, lo, hi], _pol([a, b, lo, hi]),
+                                               ev.lan_opts(tol=1e-10, nev_est=5))
+    assert len(lam) == 0 and st["status"] == 0
+
+
+def test_batch_slices_match_single_and_closed_form(ctx):
+    A = I.laplacian(40, 2)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.6, lo, hi]
+    mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 40, 10, seed=1, damping=ev.DAMP_JACKSON)
+    sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, 3, 2000)
+    ivs = [[sli[q], sli[q + 1], lo, hi] for q in range(3)]
+    pols = [_pol(iv) for iv in ivs]
+    opts = [ev.lan_opts(tol=1e-10, seed=2 + q, nev_est=int(est / 3) + 5) for q in range(3)]
+    outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
+    got = []
+    for q, (lam, Y, res, st) in enumerate(outs):
+        keep = (lam >= ivs[q][0]) & ((lam < ivs[q][1]) | (q == 2))
+        got.append(lam[keep])
+        assert res.max() <= 1e-10
+        one = ev.evsl_filtered_lanczos(ctx, Ad, ivs[q], pols[q], opts[q])[0]
+        assert len(one) == len(lam) and np.abs(one - lam).max() <= 1e-10 * 8
+    got = np.sort(np.concatenate(got))
+    want = _closed_form_interval(40, 2, 1.0, 1.6)
+    assert len(got) == 91 and np.abs(got - want).max() <= 1e-10 * 8
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    A = I.laplacian(10, 2)
+    Ad = ev.DeviceCsr.from_host(A)
+    with pytest.raises(ev.EvslError) as e:
+        ev.evsl_kpm_dos(ctx, Ad, [1.0, 2.0, 3.0, 3.0], 10, 2)
+    assert e.value.code == ev.EVSL_EINVAL
+    p = _pol([1.0, 1.5, 0.0, 8.0])
+    with pytest.raises(ev.EvslError):
+        ev.evsl_filtered_lanczos(ctx, Ad, [1.0, 1.5, 0.0, 9.0], p)   # filter built for other bounds

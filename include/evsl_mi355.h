@@ -111,7 +111,7 @@ typedef struct {
   double t_mv;    /* seconds in filter products */
   double t_orth;  /* seconds in reorthogonalisation */
   double t_ritz;  /* seconds in Rayleigh-Ritz, locking and restarts */
-  double t_tot;
+  double t_tot;   /* wall time of the call; in a batch, when this slice finished */
 } evsl_eigs_t;
 
 /* ---- context (replaces EVSLStart/EVSLFinish of Section 3.1) ----
@@ -198,6 +198,18 @@ int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, dou
 /* Releases lam, res (host) and Y (device) of a result; safe on zeroed structs. */
 void evsl_eigs_free(evsl_ctx_t ctx, evsl_eigs_t *out);
 
+/* ---- tuning ----
+ * Autotuner for the batched filter: times Chebyshev steps of A over scratch
+ * blocks of g = 1, 2, 3, 4, 5, 6, 8, ... <= max_cols columns and keeps the
+ * group width with the lowest time per column-step (a narrower group wins
+ * unless a wider one is more than 2% faster). Batches then filter their
+ * slices in groups of that width, one launch per group and degree step.
+ * Synchronous; the scratch contents are arbitrary. */
+int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_width,
+                  double *us_per_colstep);
+/* Sets the batch group width directly (0: all active slices in one group). */
+int evsl_set_group_width(evsl_ctx_t ctx, int g);
+
 /* ---- measurement helpers ----
  * Number of filter-step kernels launched and their total device time (from
  * HIP events on the context stream) since the last reset. */
@@ -205,9 +217,16 @@ int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double
 int evsl_reset_stats(evsl_ctx_t ctx);
 /* Enables (1) or disables (0) HIP-event timing of each filter application. */
 int evsl_set_timing(evsl_ctx_t ctx, int on);
-/* Selects the SpMV variant for single-vector filter steps: 0 auto, 1 direct
- * row-per-thread, 2 LDS-staged CSR stream. */
+/* Selects the kernel for single-vector filter steps: 0 auto, 1 direct
+ * row-per-thread, 2 LDS-staged CSR stream, 3 LDS-staged with the nonzero loop
+ * unrolled by 8 and XCD-contiguous workgroup order, 4 as 3 without the XCD
+ * order. */
 int evsl_set_spmv_variant(evsl_ctx_t ctx, int variant);
+/* Selects the kernel for block (several columns) filter steps, process-wide:
+ * 1 global loads, 2 LDS-staged + unrolled + XCD order with two columns per
+ * lane (16-byte loads) when the block allows it (default), 3 as 2 without the
+ * XCD order and one column per lane, 4 as 2 with one column per lane. */
+int evsl_set_block_variant(int variant);
 
 #ifdef __cplusplus
 }

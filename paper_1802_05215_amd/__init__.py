@@ -28,6 +28,7 @@ EXPORTS = [
     "evsl_cheb_coeffs", "evsl_filter_apply", "evsl_filtered_lanczos",
     "evsl_filtered_lanczos_batch", "evsl_eigs_get_vectors", "evsl_eigs_free",
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
+    "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width",
 ]
 
 
@@ -101,6 +102,9 @@ def _lib():
         L.evsl_reset_stats.argtypes = [C.c_void_p]
         L.evsl_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.evsl_set_spmv_variant.argtypes = [C.c_void_p, C.c_int]
+        L.evsl_set_block_variant.argtypes = [C.c_int]
+        L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.POINTER(C.c_int), _dp]
+        L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
         _LIB = L
     return _LIB
 
@@ -108,6 +112,10 @@ def _lib():
 def load():
     """Load the native library (raises ImportError when it is not built)."""
     return _lib()
+
+
+def evsl_set_block_variant(v):
+    _chk(_lib().evsl_set_block_variant(int(v)), "evsl_set_block_variant")
 
 
 def _chk(rc, where, ok=(EVSL_OK,)):
@@ -161,6 +169,18 @@ class Ctx:
 
     def set_spmv_variant(self, v):
         _chk(_lib().evsl_set_spmv_variant(self.h, int(v)), "set_spmv_variant")
+
+    def set_group_width(self, g):
+        _chk(_lib().evsl_set_group_width(self.h, int(g)), "set_group_width")
+
+
+def evsl_autotune(ctx, A, max_cols):
+    """Returns (group width, microseconds per column-step)."""
+    g = C.c_int()
+    us = C.c_double()
+    _chk(_lib().evsl_autotune(ctx.h, C.byref(A.t), int(max_cols), C.byref(g), C.byref(us)),
+         "evsl_autotune")
+    return g.value, us.value
 
 
 class DeviceCsr:

@@ -40,6 +40,16 @@ __device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Remapping gives XCD x a contiguous range of logical blocks, so rows
+// that are neighbours in the matrix (and read each other's vector entries)
+// are processed by the same XCD, one after another.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int x = bid & 7, local = bid >> 3;
+  const int q = nblk >> 3, rem = nblk & 7;
+  return x * q + min(x, rem) + local;
+}
+
 // ---------------------------------------------------------------- filter step, single vectors
 // One row per thread; grid.y selects the column of a column-major multivector.
 template <typename T, int KIND>
@@ -126,6 +136,74 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds(int n, const int *__restri
   }
 }
 
+// LDS-staged CSR stream with the nonzero loop unrolled by 8: the column
+// indices and values of 8 entries come from LDS, their 8 gathers are issued
+// together (padding entries read element 0 and are multiplied by 0), then
+// accumulated in index order. XCD=true remaps workgroups per XCD.
+template <typename T, int KIND, bool XCD>
+__global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restrict__ rp,
+                                                       const int *__restrict__ ci,
+                                                       const T *__restrict__ va, T s1, T s0,
+                                                       const T *__restrict__ W, const T *Wp, T *Wn,
+                                                       T *Y, int64_t ld,
+                                                       const double *__restrict__ coef, int cld,
+                                                       int jnext) {
+  constexpr int CAP = 2048;
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+  constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
+  constexpr bool Y_INIT = (KIND == STEP_FIRST);
+  __shared__ int s_rp[TPB + 1];
+  __shared__ int s_ci[CAP];
+  __shared__ T s_va[CAP];
+  const int bx = XCD ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int r0 = bx * TPB;
+  const int nr = min(TPB, n - r0);
+  for (int i = threadIdx.x; i <= nr; i += TPB) s_rp[i] = rp[r0 + i];
+  __syncthreads();
+  const int nz0 = s_rp[0];
+  const int cnt = s_rp[nr] - nz0;
+  const bool staged = cnt <= CAP;
+  if (staged) {
+    for (int i = threadIdx.x; i < cnt; i += TPB) {
+      s_ci[i] = ci[nz0 + i];
+      s_va[i] = va[nz0 + i];
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= nr) return;
+  const int r = r0 + t;
+  const int64_t off = (int64_t)blockIdx.y * ld;
+  const T *w = W + off;
+  T acc = 0;
+  const int kb = s_rp[t] - nz0, ke = s_rp[t + 1] - nz0;
+  if (staged) {
+    for (int k = kb; k < ke; k += 8) {
+      T a[8], g[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = k + u < ke;
+        const int c = ok ? s_ci[k + u] : 0;
+        a[u] = ok ? s_va[k + u] : (T)0;
+        g[u] = w[c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
+    }
+  } else {
+    for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * w[ci[k]];
+  }
+  const T wr = w[r];
+  T wn = s1 * acc + s0 * wr;
+  if (HAS_PREV) wn -= Wp[off + r];
+  Wn[off + r] = wn;
+  if (HAS_Y) {
+    const double *cc = coef + (int64_t)blockIdx.y * cld;
+    const T y = Y_INIT ? (T)cc[0] * wr : Y[off + r];
+    Y[off + r] = y + (T)cc[jnext] * wn;
+  }
+}
+
 template <typename T>
 void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, double s0,
               const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
@@ -136,7 +214,21 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
 #define EVK_LAUNCH_VEC(KERN, K)                                                               \
   hipLaunchKernelGGL((KERN<T, K>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, \
                      Wp, Wn, Y, ld, coef, cld, jnext)
-  if (variant == 2) {
+  if (variant == 3 || variant == 4) {
+    if (variant == 3) {
+      switch (kind) {
+        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+      }
+    } else {
+      switch (kind) {
+        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+      }
+    }
+  } else if (variant == 2) {
     switch (kind) {
       case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_PLAIN); break;
       case STEP_FIRST: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_FIRST); break;
@@ -223,19 +315,146 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
   }
 }
 
-static void blk_shape(int n, int nc, int *rows_per_wg, dim3 *grid) {
-  int R0 = nc <= TPB ? TPB / nc : 1;
-  int passes = 4;
+// Row-major block, LDS-staged: the workgroup's rows of the CSR matrix are
+// loaded into LDS with coalesced loads; each thread owns VEC adjacent columns
+// of a group of rows (columns fastest, so the epilogue is contiguous), reads
+// the row's entries from LDS and issues 8 gathers of VEC values at a time.
+// Offsets are 32-bit (the host selects this kernel only when n * ld < 2^31);
+// VEC > 1 needs nc and ld divisible by VEC and VEC-aligned base pointers.
+template <typename T, int KIND, bool XCD, int VEC>
+__global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_per_wg,
+                                                      const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const T *__restrict__ va, T s1, T s0,
+                                                      const T *__restrict__ W, const T *Wp, T *Wn,
+                                                      T *Y, int64_t ld64,
+                                                      const double *__restrict__ coef, int cld,
+                                                      int jnext, const T *__restrict__ Vd,
+                                                      double *partial) {
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  constexpr int CAP = 1792;
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT);
+  constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
+  constexpr bool Y_INIT = (KIND == STEP_FIRST);
+  constexpr bool HAS_DOT = (KIND == STEP_KPM_FIRST || KIND == STEP_KPM_NEXT);
+  __shared__ int s_rp[TPB + 1];
+  __shared__ int s_ci[CAP];
+  __shared__ T s_va[CAP];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int bx = XCD ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int r0 = bx * rows_per_wg;
+  const int nr = min(rows_per_wg, n - r0);
+  for (int i = tid; i <= nr; i += TPB) s_rp[i] = rp[r0 + i];
+  __syncthreads();
+  const int nz0 = s_rp[0];
+  const int cnt = s_rp[nr] - nz0;
+  const bool staged = cnt <= CAP;
+  if (staged) {
+    for (int i = tid; i < cnt; i += TPB) {
+      s_ci[i] = ci[nz0 + i];
+      s_va[i] = va[nz0 + i];
+    }
+  }
+  __syncthreads();
+  const int ncv = nc / VEC;  // vector slots per row
+  int R0, rsub, slot;
+  bool active;
+  if (ncv <= TPB) {
+    R0 = TPB / ncv;
+    rsub = tid / ncv;
+    slot = tid - rsub * ncv;
+    active = rsub < R0;
+  } else {
+    R0 = 1;
+    rsub = 0;
+    slot = blockIdx.y * TPB + tid;
+    active = slot < ncv;
+  }
+  const int col = slot * VEC;
+  const int ld = (int)ld64;
+  double dacc = 0.0;
+  if (active) {
+    vt c0 = (T)0, c1 = (T)0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      if (HAS_Y) {
+        c1[v] = (T)coef[(col + v) * cld + jnext];
+        if (Y_INIT) c0[v] = (T)coef[(col + v) * cld];
+      }
+    }
+    const T *wc = W + col;
+    for (int rl = rsub; rl < nr; rl += R0) {
+      const int kb = s_rp[rl] - nz0, ke = s_rp[rl + 1] - nz0;
+      vt acc = (T)0;
+      if (staged) {
+        for (int k = kb; k < ke; k += 8) {
+          T a[8];
+          vt g[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const bool ok = k + u < ke;
+            const int c = ok ? s_ci[k + u] : 0;
+            a[u] = ok ? s_va[k + u] : (T)0;
+            g[u] = *(const vt *)(wc + c * ld);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
+        }
+      } else {
+        for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * *(const vt *)(wc + ci[k] * ld);
+      }
+      const int e = (r0 + rl) * ld + col;
+      const vt w = *(const vt *)(W + e);
+      vt wn = s1 * acc + s0 * w;
+      if (HAS_PREV) wn -= *(const vt *)(Wp + e);
+      *(vt *)(Wn + e) = wn;
+      if (HAS_Y) {
+        const vt y = Y_INIT ? c0 * w : *(const vt *)(Y + e);
+        *(vt *)(Y + e) = y + c1 * wn;
+      }
+      if (HAS_DOT) {
+        const vt vd = *(const vt *)(Vd + e);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) dacc += (double)vd[v] * (double)wn[v];
+      }
+    }
+  }
+  if (HAS_DOT) {
+    const double b = block_sum(dacc, red);
+    if (tid == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+static int g_blk_variant = 2;  // 1: global loads, 2: LDS + XCD remap, 3: LDS, 4: 2 as VEC 1
+
+void set_blk_variant(int v) { g_blk_variant = (v >= 1 && v <= 4) ? v : 2; }
+
+// Columns per lane for a launch: 2 (16-byte loads) when the block allows it.
+static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int np) {
+  if (g_blk_variant == 4 || g_blk_variant == 1 || es != 8) return 1;
+  if ((nc & 1) || (ld & 1)) return 1;
+  for (int i = 0; i < np; ++i)
+    if (ptrs[i] && ((uintptr_t)ptrs[i] & 15)) return 1;
+  return 2;
+}
+
+static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid) {
+  const int ncv = nc / vec;
+  const int R0 = ncv <= TPB ? TPB / ncv : 1;
+  int passes = ncv <= TPB ? 4 : 8;
+  if (g_blk_variant != 1) passes = std::max(1, std::min(passes, TPB / R0));
   *rows_per_wg = R0 * passes;
-  int gx = (n + *rows_per_wg - 1) / *rows_per_wg;
-  int gy = nc <= TPB ? 1 : (nc + TPB - 1) / TPB;
+  const int gx = (n + *rows_per_wg - 1) / *rows_per_wg;
+  const int gy = ncv <= TPB ? 1 : (ncv + TPB - 1) / TPB;
   *grid = dim3(gx, gy);
 }
 
 int blk_partials(int n, int nc) {
+  // an upper bound over the launch shapes (VEC 1 has the most workgroups)
   int rpw;
   dim3 g;
-  blk_shape(n, nc, &rpw, &g);
+  blk_shape(n, nc, 1, &rpw, &g);
   return (int)(g.x * g.y);
 }
 
@@ -244,13 +463,28 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
               const T *Vd, double *partial) {
   if (A.n <= 0 || nc <= 0) return;
+  const bool small = (int64_t)A.n * ld < ((int64_t)1 << 31) && (int64_t)nc * cld < ((int64_t)1 << 31);
+  const int var = small ? g_blk_variant : 1;
+  const void *ptrs[5] = {W, Wp, Wn, Y, Vd};
+  const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5);
   int rpw;
   dim3 grid;
-  blk_shape(A.n, nc, &rpw, &grid);
+  blk_shape(A.n, nc, vec, &rpw, &grid);
   const T *va = (const T *)A.va;
-#define EVK_LAUNCH_BLK(K)                                                                       \
-  hipLaunchKernelGGL((k_cheb_blk<T, K>), grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, \
-                     (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd, partial)
+#define EVK_BLK_ARGS                                                                          \
+  grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, \
+      jnext, Vd, partial
+#define EVK_LAUNCH_BLK(K)                                                                    \
+  do {                                                                                       \
+    if (var == 1)                                                                            \
+      hipLaunchKernelGGL((k_cheb_blk<T, K>), EVK_BLK_ARGS);                                  \
+    else if (var == 3)                                                                       \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1>), EVK_BLK_ARGS);                    \
+    else if (vec == 2)                                                                       \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2>), EVK_BLK_ARGS);                     \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1>), EVK_BLK_ARGS);                     \
+  } while (0)
   switch (kind) {
     case STEP_PLAIN: EVK_LAUNCH_BLK(STEP_PLAIN); break;
     case STEP_FIRST: EVK_LAUNCH_BLK(STEP_FIRST); break;
@@ -259,6 +493,7 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
     default: EVK_LAUNCH_BLK(STEP_KPM_NEXT); break;
   }
 #undef EVK_LAUNCH_BLK
+#undef EVK_BLK_ARGS
 }
 
 template void cheb_blk<double>(hipStream_t, const Csr &, int, double, double, const double *,

@@ -38,6 +38,8 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
               const T *Vd, double *partial);
 int blk_partials(int n, int nc);
+// Block kernel choice: 1 global loads, 2 LDS-staged + XCD remap (default), 3 LDS-staged.
+void set_blk_variant(int v);
 
 // Gather / scatter single columns into / out of a row-major block:
 // blk[r * ldb + c] = src[c][r] for c < nc (pointers in a device array).

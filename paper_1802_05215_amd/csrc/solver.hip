@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -36,7 +37,8 @@ struct evsl_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
   int last_hip = 0;
-  int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged
+  int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged, 3/4 unrolled
+  int group_width = 0;   // columns per block filter launch in batches (0: all)
   bool timing = true;
   // filter measurement
   int64_t filt_launches = 0;
@@ -187,7 +189,7 @@ double step_bytes(const evsl_csr_t *A, int nc, int s, int passes) {
   return ma + (double)passes * (double)A->n * nc * s;
 }
 
-int pick_variant(evsl_ctx_t ctx) { return ctx->spmv_variant == 0 ? 2 : ctx->spmv_variant; }
+int pick_variant(evsl_ctx_t ctx) { return ctx->spmv_variant == 0 ? 3 : ctx->spmv_variant; }
 
 // --------------------------------------------------------------------------
 // Orthogonalisation helpers on a column-major basis B (n x *, leading dim ld).
@@ -252,7 +254,7 @@ struct Slice {
   bool done = false;
   int status = EVSL_OK;
   bool next_ok = true;
-  double t_mv = 0, t_orth = 0, t_ritz = 0;
+  double t_mv = 0, t_orth = 0, t_ritz = 0, t_done = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 
   Slice() = default;
@@ -366,11 +368,20 @@ struct Slice {
 
   // Single-slice filter: z = rho(A-hat) q_i by the three-term recurrence.
   void filter_single() {
+    FilterTimer tm(ctx);
+    HC(ctx, hipEventRecord(ev0, st()));
+    filter_vector_async();
+    HC(ctx, hipEventRecord(ev1, st()));
+    const double b0 = step_bytes(A, 1, 8, 3), b1 = step_bytes(A, 1, 8, 5);
+    tm.stop(deg, b0 + (deg - 1) * b1);
+    nmv += deg;
+  }
+
+  // The deg launches of the filter on q_i (single-vector kernel), z = output.
+  void filter_vector_async() {
     const evk::Csr Ac = to_csr(A);
     const int var = pick_variant(ctx);
     const double *q = current();
-    FilterTimer tm(ctx);
-    HC(ctx, hipEventRecord(ev0, st()));
     // W_1 = (A q - c q)/d; Y = c0 q + c1 W_1
     evk::cheb_vec<double>(st(), Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z,
                           ld, 1, coef_dev, deg + 1, 1);
@@ -384,10 +395,6 @@ struct Slice {
       wprev = wcur;
       wcur = dst;
     }
-    HC(ctx, hipEventRecord(ev1, st()));
-    const double b0 = step_bytes(A, 1, 8, 3), b1 = step_bytes(A, 1, 8, 5);
-    tm.stop(deg, b0 + (deg - 1) * b1);
-    nmv += deg;
   }
 
   // Orthogonalise z against [locked, q_1..q_i], normalise into q_{i+1} and
@@ -683,9 +690,75 @@ int evsl_set_timing(evsl_ctx_t ctx, int on) {
 }
 
 int evsl_set_spmv_variant(evsl_ctx_t ctx, int variant) {
-  if (!ctx || variant < 0 || variant > 2) return EVSL_EINVAL;
+  if (!ctx || variant < 0 || variant > 4) return EVSL_EINVAL;
   ctx->spmv_variant = variant;
   return EVSL_OK;
+}
+
+int evsl_set_block_variant(int variant) {
+  if (variant < 1 || variant > 4) return EVSL_EINVAL;
+  evk::set_blk_variant(variant);
+  return EVSL_OK;
+}
+
+int evsl_set_group_width(evsl_ctx_t ctx, int g) {
+  if (!ctx || g < 0) return EVSL_EINVAL;
+  ctx->group_width = g;
+  return EVSL_OK;
+}
+
+int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_width,
+                  double *us_per_colstep) {
+  if (!ctx || max_cols < 1) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const int n = (int)A->n;
+  hipStream_t s = ctx->stream;
+  const size_t blk = (size_t)n * max_cols;
+  double *X0 = (double *)ws(ctx, 20, sizeof(double) * blk);
+  double *X1 = (double *)ws(ctx, 21, sizeof(double) * blk);
+  double *Yb = (double *)ws(ctx, 22, sizeof(double) * blk);
+  double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)max_cols * 4);
+  HC(ctx, hipMemsetAsync(ctab, 0, sizeof(double) * (size_t)max_cols * 4, s));
+  evk::rademacher(s, n, max_cols, 11, X0);
+  evk::rademacher(s, n, max_cols, 12, X1);
+  const evk::Csr Ac = to_csr(A);
+  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+  const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
+  const int reps = 8;
+  double best = 1e300;
+  int bestg = max_cols;
+  // a contractive scaling keeps the scratch values bounded over the timed steps
+  const double sc = 1e-3;
+  for (int g : cand) {
+    if (g > max_cols) break;
+    for (int r = -2; r < reps; ++r) {
+      if (r == 0) HC(ctx, hipEventRecord(e0, s));
+      if (g == 1)
+        evk::cheb_vec<double>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, X1, X0, X0, Yb, n,
+                              1, ctab, 4, 1);
+      else
+        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, sc, 0.0, X1, X0, X0, Yb, g, g, ctab, 4, 1,
+                              nullptr, nullptr);
+    }
+    HC(ctx, hipEventRecord(e1, s));
+    HC(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HC(ctx, hipEventElapsedTime(&ms, e0, e1));
+    const double us = ms * 1e3 / reps / g;
+    if (us < best * 0.98) {  // prefer narrower groups unless wider ones win clearly
+      best = us;
+      bestg = g;
+    }
+  }
+  ctx->event_pool.push_back(e0);
+  ctx->event_pool.push_back(e1);
+  ctx->group_width = bestg;
+  if (group_width) *group_width = bestg;
+  if (us_per_colstep) *us_per_colstep = best;
+  return EVSL_OK;
+  EVSL_GUARD_END
 }
 
 int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes) {
@@ -771,6 +844,8 @@ int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int 
   double *mom_dev = (double *)ws(ctx, 4, sizeof(double) * (degree + 2));
   hipStream_t s = ctx->stream;
   const evk::Csr Ac = to_csr(A);
+  // launches may write fewer partials than the bound nw (wider vector slots)
+  HC(ctx, hipMemsetAsync(part, 0, sizeof(double) * (size_t)nw * (degree + 1), s));
   evk::rademacher(s, n, nvec, seed, V);
   // zeta_0 = (1/nvec) V . V
   evk::col_dots(s, (int)blk, 1, V, 0, V, 0, part + (size_t)nw * (degree + 1), mom_dev);
@@ -1016,8 +1091,20 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   double *X1 = (double *)ws(ctx, 21, sizeof(double) * (size_t)n * nslices);
   double *Yb = (double *)ws(ctx, 22, sizeof(double) * (size_t)n * nslices);
   double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)nslices * (kmax + 1));
-  double **ptrs = (double **)ws(ctx, 24, sizeof(double *) * 2 * nslices);
+  double **ptrs = (double **)ws(ctx, 24, sizeof(double *) * 2 * (nslices + 1));
+  // pinned staging for the per-group pointer arrays (copied asynchronously)
+  struct PinnedPtrs {
+    void *p = nullptr;
+    ~PinnedPtrs() {
+      if (p) (void)hipHostFree(p);
+    }
+  } hptrs;
+  HC(ctx, hipHostMalloc(&hptrs.p, sizeof(double *) * 2 * (nslices + 1), hipHostMallocDefault));
+  const double **hsrc = (const double **)hptrs.p;
   const evk::Csr Ac = to_csr(A);
+  const char *prog_env = std::getenv("EVSL_PROGRESS");
+  const int progress = prog_env ? std::atoi(prog_env) : 0;
+  long global_step = 0;
   std::vector<int> act, prev_act;
   std::vector<double> tab;
   std::vector<int> ncs(kmax + 2);
@@ -1042,46 +1129,72 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       }
       prev_act = act;
     }
-    // gather the current Lanczos vectors of the active slices, filter them
-    // together, scatter the results
-    std::vector<const double *> src(na);
-    std::vector<double *> dst(na);
-    for (int c = 0; c < na; ++c) {
-      src[c] = sl[act[c]].current();
-      dst[c] = sl[act[c]].z;
-    }
-    HC(ctx, hipMemcpyAsync(ptrs, src.data(), sizeof(double *) * na, hipMemcpyHostToDevice, s));
-    HC(ctx, hipMemcpyAsync(ptrs + nslices, dst.data(), sizeof(double *) * na,
-                           hipMemcpyHostToDevice, s));
-    evk::gather_cols(s, n, na, (const double *const *)ptrs, X0, na);
+    // filter the current Lanczos vectors of the active slices, group by group
+    // (consecutive slices in degree order; one block launch per degree step)
+    const int gw = ctx->group_width > 0 ? std::min(ctx->group_width, na) : na;
     FilterTimer tm(ctx);
     for (int q : act) HC(ctx, hipEventRecord(sl[q].ev0, s));
     double bytes = 0.0;
-    evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, na,
-                          ncs[1], ctab, km + 1, 1, nullptr, nullptr);
-    bytes += step_bytes(A, ncs[1], 8, 3);
-    // X0 = W_0, X1 = W_1; W_{j+1} is written over W_{j-1}
-    double *wprev = X0, *wcur = X1;
-    for (int j = 1; j < km; ++j) {
-      evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
-                            Yb, na, ncs[j + 1], ctab, km + 1, j + 1, nullptr, nullptr);
-      bytes += step_bytes(A, ncs[j + 1], 8, 5);
-      std::swap(wprev, wcur);
+    int64_t launches = 0;
+    for (int g0 = 0; g0 < na; g0 += gw) {
+      const int gn = std::min(gw, na - g0);
+      int gk = 0;
+      for (int c = 0; c < gn; ++c) gk = std::max(gk, sl[act[g0 + c]].deg);
+      if (gn == 1) {
+        Slice &S = sl[act[g0]];
+        S.filter_vector_async();
+        bytes += step_bytes(A, 1, 8, 3) + (S.deg - 1) * step_bytes(A, 1, 8, 5);
+        launches += S.deg;
+        continue;
+      }
+      const double **hg = hsrc + 2 * g0;
+      for (int c = 0; c < gn; ++c) {
+        hg[c] = sl[act[g0 + c]].current();
+        hg[gn + c] = sl[act[g0 + c]].z;
+      }
+      double **gp = ptrs + 2 * g0;
+      HC(ctx, hipMemcpyAsync(gp, hg, sizeof(double *) * 2 * gn, hipMemcpyHostToDevice, s));
+      evk::gather_cols(s, n, gn, (const double *const *)gp, X0, gn);
+      const double *gtab = ctab + (size_t)g0 * (km + 1);
+      evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, gn,
+                            ncs[1] - g0 >= gn ? gn : std::max(ncs[1] - g0, 1), gtab, km + 1, 1,
+                            nullptr, nullptr);
+      bytes += step_bytes(A, gn, 8, 3);
+      // X0 = W_0, X1 = W_1; W_{j+1} is written over W_{j-1}
+      double *wprev = X0, *wcur = X1;
+      for (int j = 1; j < gk; ++j) {
+        const int ncj = std::min(gn, std::max(ncs[j + 1] - g0, 1));
+        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
+                              Yb, gn, ncj, gtab, km + 1, j + 1, nullptr, nullptr);
+        bytes += step_bytes(A, ncj, 8, 5);
+        std::swap(wprev, wcur);
+      }
+      launches += gk;
+      evk::scatter_cols(s, n, gn, Yb, gn, (double *const *)(gp + gn));
     }
     for (int q : act) HC(ctx, hipEventRecord(sl[q].ev1, s));
-    tm.stop(km, bytes);
-    evk::scatter_cols(s, n, na, Yb, na, (double *const *)(ptrs + nslices));
+    tm.stop(launches, bytes);
     for (int q : act) {
       sl[q].nmv += sl[q].deg;
       sl[q].orth_and_queue();
     }
     HC(ctx, hipStreamSynchronize(s));
-    for (int q : act) sl[q].after_step();
+    for (int q : act) {
+      sl[q].after_step();
+      if (sl[q].done) sl[q].t_done = now_s() - t0;
+    }
+    ++global_step;
+    if (progress > 0 && global_step % progress == 0) {
+      int nl = 0;
+      for (auto &x : sl) nl += x.nlock;
+      std::fprintf(stderr, "[evsl] step %ld: %d slices active, %d pairs locked, %.1f s\n",
+                   global_step, na, nl, now_s() - t0);
+    }
   }
   int rc = EVSL_OK;
   for (int q = 0; q < nslices; ++q) {
     sl[q].emit(&outs[q]);
-    outs[q].t_tot = now_s() - t0;
+    outs[q].t_tot = sl[q].t_done;  // completion time of this slice within the batch
     if (outs[q].status != EVSL_OK) rc = outs[q].status;
   }
   return rc;

@@ -39,7 +39,7 @@ def _pol(intv, damp=ev.DAMP_JACKSON):
     return ev.evsl_cheb_coeffs(intv, damping=damp, tau=0.8, tau_ext=0.4)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 @pytest.mark.parametrize("N,dim,pot,intv", [(40, 2, None, [1.0, 1.6, 0.0, 8.0]),
                                             (13, 3, 0, [2.0, 2.3, 0.0, 13.0]),
                                             (23, 2, 5, [0.0, 0.7, 0.0, 9.0])])
@@ -59,8 +59,10 @@ def test_filter_single_vector_matches_oracle(ctx, variant, N, dim, pot, intv):
     ctx.set_spmv_variant(0)
 
 
+@pytest.mark.parametrize("blk_variant", [1, 2, 3])
 @pytest.mark.parametrize("sorted_cols", [True, False])
-def test_filter_block_matches_oracle(ctx, sorted_cols):
+def test_filter_block_matches_oracle(ctx, sorted_cols, blk_variant):
+    ev.evsl_set_block_variant(blk_variant)
     A = I.laplacian(37, 2, pot_seed=1)             # n = 1369: ragged against every tile
     Ad = ev.DeviceCsr.from_host(A)
     lo, hi = 0.0, 9.0
@@ -84,9 +86,62 @@ def test_filter_block_matches_oracle(ctx, sorted_cols):
         err = np.linalg.norm(Yh[:, c] - ref) / np.linalg.norm(Vh[:, c])
         assert err <= 1e-11, (c, err)
     assert np.all(Yh[:, ncols:] == 0.0)           # padding columns untouched
+    ev.evsl_set_block_variant(2)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("blk_variant", [1, 2])
+@pytest.mark.parametrize("ncols", [16, 300])
+def test_filter_wide_block_matches_oracle(ctx, ncols, blk_variant):
+    """Blocks wider than one workgroup row (300 > 256 columns) and rows with
+    more nonzeros than the LDS stage holds fall back correctly."""
+    ev.evsl_set_block_variant(blk_variant)
+    A = I.laplacian(9, 3, pot_seed=2)
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol([2.0, 2.4, 0.0, 13.0])
+    rng = np.random.default_rng(8)
+    Vh = rng.standard_normal((A.n, ncols))
+    V = _dev(Vh)
+    Y = torch.empty_like(V)
+    ev.evsl_filter_apply(ctx, Ad, [p], [0] * ncols, V, Y)
+    torch.cuda.synchronize()
+    ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, Vh)
+    err = np.linalg.norm(Y.cpu().numpy() - ref, axis=0) / np.linalg.norm(Vh, axis=0)
+    assert err.max() <= 1e-11
+    ev.evsl_set_block_variant(2)
+
+
+def test_filter_dense_rows_fall_back(ctx):
+    """A matrix whose rows exceed the LDS stage (a dense 300 x 300 block)."""
+    rng = np.random.default_rng(2)
+    n = 300
+    M = rng.standard_normal((n, n))
+    M = (M + M.T) / 2
+    M /= np.abs(np.linalg.eigvalsh(M)).max()
+    rows, cols = np.nonzero(np.ones((n, n)))
+    A = I.CSR(n, np.arange(0, n * n + 1, n).astype(np.int32), cols.astype(np.int32),
+              M[rows, cols].copy())
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol([0.1, 0.3, -1.0, 1.0])
+    v = rng.standard_normal(n)
+    ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, v)
+    for var in (1, 2, 3, 4):
+        ctx.set_spmv_variant(var)
+        Y = torch.empty(n, dtype=torch.float64, device="cuda")
+        ev.evsl_filter_apply(ctx, Ad, [p], [0], _dev(v), Y)
+        torch.cuda.synchronize()
+        assert np.linalg.norm(Y.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(v), var
+    for bv in (1, 2, 3):
+        ev.evsl_set_block_variant(bv)
+        V2 = _dev(np.stack([v, 2 * v], axis=1))
+        Y2 = torch.empty_like(V2)
+        ev.evsl_filter_apply(ctx, Ad, [p], [0, 0], V2, Y2)
+        torch.cuda.synchronize()
+        assert np.linalg.norm(Y2.cpu().numpy()[:, 1] - 2 * ref) <= 2e-11 * np.linalg.norm(v), bv
+    ctx.set_spmv_variant(0)
+    ev.evsl_set_block_variant(2)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_filter_closed_form_eigenvector_full_size(ctx, variant):
     # 100^3 Laplacian (n = 1e6, the plain-method matrix without its potential)
     N = 100
@@ -229,7 +284,12 @@ def test_filtered_lanczos_empty_slice(ctx):
     assert len(lam) == 0 and st["status"] == 0
 
 
-def test_batch_slices_match_single_and_closed_form(ctx):
+@pytest.mark.parametrize("group", [0, 1, 2])
+def test_batch_slices_match_single_and_closed_form(ctx, group):
+    """Three KPM slices solved together; group 0 filters all slices in one
+    block launch per degree step, 1 uses the single-vector kernel per slice,
+    2 splits them into groups of two and one."""
+    ctx.set_group_width(group)
     A = I.laplacian(40, 2)
     Ad = ev.DeviceCsr.from_host(A)
     lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
@@ -250,6 +310,15 @@ def test_batch_slices_match_single_and_closed_form(ctx):
     got = np.sort(np.concatenate(got))
     want = _closed_form_interval(40, 2, 1.0, 1.6)
     assert len(got) == 91 and np.abs(got - want).max() <= 1e-10 * 8
+    ctx.set_group_width(0)
+
+
+def test_autotune_picks_a_width_and_batches_still_agree(ctx):
+    A = I.laplacian(30, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    g, us = ev.evsl_autotune(ctx, Ad, 6)
+    assert 1 <= g <= 6 and us > 0
+    ctx.set_group_width(0)
 
 
 def test_invalid_arguments_are_rejected(ctx):

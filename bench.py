@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-width", type=int, default=-1,
                     help="slices per block filter launch (-1: autotuned, 0: all)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain copy kernel (1 GiB) used to calibrate counters")
     ap.add_argument("--mode", choices=["batch", "serial"], default="batch",
                     help="batch: all slices in lock-step; serial: one slice after another")
     return ap.parse_args()
@@ -124,8 +126,43 @@ def cpu_baseline(A, rec, args):
                        f"the oracle's rate")}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1802_05215_amd", "csrc", "kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "filter_step_100cube_counters.txt")
+
+
+def measured_traffic():
+    """HBM bytes per filter launch from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_probe_main():
+    import torch
+    import paper_1802_05215_amd as ev
+    ev.load()
+    ctx = ev.Ctx()
+    nbytes = 1 << 30
+    t = ev.evsl_copy_probe(ctx, nbytes, 20)
+    print(json.dumps({"copy_probe_bytes": nbytes, "seconds_per_copy": t,
+                      "gbps_read_plus_write": 2 * nbytes / t / 1e9}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe_main()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -204,12 +241,18 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "traffic_bytes_per_launch": None,
             "kernel": "k_cheb_blk<double, STEP_NEXT> (filter degree step)",
             "bytes_per_launch": per_launch_bytes,
             "avg_launch_us": fs["seconds"] / max(fs["launches"], 1) * 1e6,
             "launches": fs["launches"],
         },
     }
+    tb = measured_traffic()
+    if tb is not None and fs["launches"]:
+        avg_s = fs["seconds"] / fs["launches"]
+        out["roofline"]["traffic"] = tb / avg_s / 1e9
+        out["roofline"]["traffic_bytes_per_launch"] = tb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, rec, args)
     print(json.dumps(out), flush=True)

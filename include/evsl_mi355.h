@@ -215,6 +215,11 @@ int evsl_set_group_width(evsl_ctx_t ctx, int g);
  * HIP events on the context stream) since the last reset. */
 int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes);
 int evsl_reset_stats(evsl_ctx_t ctx);
+/* Bandwidth reference: `reps` launches of a plain copy kernel reading and
+ * writing `bytes` bytes (rounded down to a multiple of 16) of context
+ * workspace; returns the average seconds per copy (HIP events). Used to
+ * calibrate hardware traffic counters. Synchronous. */
+int evsl_copy_probe(evsl_ctx_t ctx, int64_t bytes, int reps, double *seconds_per_copy);
 /* Enables (1) or disables (0) HIP-event timing of each filter application. */
 int evsl_set_timing(evsl_ctx_t ctx, int on);
 /* Selects the kernel for single-vector filter steps: 0 auto, 1 direct

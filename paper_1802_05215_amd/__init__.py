@@ -28,7 +28,7 @@ EXPORTS = [
     "evsl_cheb_coeffs", "evsl_filter_apply", "evsl_filtered_lanczos",
     "evsl_filtered_lanczos_batch", "evsl_eigs_get_vectors", "evsl_eigs_free",
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
-    "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width",
+    "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
 ]
 
 
@@ -105,6 +105,7 @@ def _lib():
         L.evsl_set_block_variant.argtypes = [C.c_int]
         L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
+        L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
         _LIB = L
     return _LIB
 
@@ -172,6 +173,13 @@ class Ctx:
 
     def set_group_width(self, g):
         _chk(_lib().evsl_set_group_width(self.h, int(g)), "set_group_width")
+
+
+def evsl_copy_probe(ctx, nbytes, reps=20):
+    """Seconds per launch of a plain copy of nbytes (read nbytes + write nbytes)."""
+    t = C.c_double()
+    _chk(_lib().evsl_copy_probe(ctx.h, int(nbytes), int(reps), C.byref(t)), "evsl_copy_probe")
+    return t.value
 
 
 def evsl_autotune(ctx, A, max_cols):

@@ -783,6 +783,22 @@ void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double 
                      x);
 }
 
+// ---------------------------------------------------------------- copy (bandwidth calibration)
+__global__ __launch_bounds__(TPB) void k_copy_probe(int64_t n2, const double2 *__restrict__ x,
+                                                    double2 *__restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n2; i += (int64_t)gridDim.x * TPB)
+    y[i] = x[i];
+}
+
+void copy_probe(hipStream_t s, int64_t bytes, const void *x, void *y) {
+  const int64_t n2 = bytes / 16;
+  if (n2 <= 0) return;
+  const int64_t want = (n2 + TPB - 1) / TPB;
+  const unsigned grid = (unsigned)std::min<int64_t>(want, 256 * 64);
+  hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(TPB), 0, s, n2, (const double2 *)x,
+                     (double2 *)y);
+}
+
 // ---------------------------------------------------------------- conversions
 __global__ __launch_bounds__(TPB) void k_to_f32(int64_t n, const double *x, float *y) {
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;

@@ -76,6 +76,8 @@ void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double 
 // out[c] = scale * sum_w partial[c * nw + w].
 void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
                      double *out);
+// Plain copy of `bytes` (a multiple of 16) from x to y: the bandwidth reference.
+void copy_probe(hipStream_t s, int64_t bytes, const void *x, void *y);
 // y = float(x) / x = double(y)
 void to_f32(hipStream_t s, int64_t n, const double *x, float *y);
 void to_f64(hipStream_t s, int64_t n, const float *x, double *y);

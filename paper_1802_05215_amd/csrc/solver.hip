@@ -761,6 +761,28 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_
   EVSL_GUARD_END
 }
 
+int evsl_copy_probe(evsl_ctx_t ctx, int64_t bytes, int reps, double *seconds_per_copy) {
+  if (!ctx || bytes < 16 || reps < 1 || !seconds_per_copy) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  bytes = bytes / 16 * 16;
+  hipStream_t s = ctx->stream;
+  void *x = ws(ctx, 30, (size_t)bytes), *y = ws(ctx, 31, (size_t)bytes);
+  HC(ctx, hipMemsetAsync(x, 0, (size_t)bytes, s));
+  evk::copy_probe(s, bytes, x, y);  // untimed first touch
+  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+  HC(ctx, hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) evk::copy_probe(s, bytes, x, y);
+  HC(ctx, hipEventRecord(e1, s));
+  HC(ctx, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HC(ctx, hipEventElapsedTime(&ms, e0, e1));
+  ctx->event_pool.push_back(e0);
+  ctx->event_pool.push_back(e1);
+  *seconds_per_copy = ms * 1e-3 / reps;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
 int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes) {
   if (!ctx) return EVSL_EINVAL;
   EVSL_GUARD_BEGIN

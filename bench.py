@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-width", type=int, default=-1,
                     help="slices per block filter launch (-1: autotuned, 0: all)")
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64",
+                    help="filter arithmetic (f32: precision form with FP64 polish)")
+    ap.add_argument("--tol-lo", type=float, default=0.0, help="FP32-phase lock tolerance")
+    ap.add_argument("--polish-div", type=int, default=0, help="polish filter degree divisor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain copy kernel (1 GiB) used to calibrate counters")
     ap.add_argument("--mode", choices=["batch", "serial"], default="batch",
@@ -71,9 +75,12 @@ def one_step(ctx, ev, Ad, args):
         ivs.append(iv)
         pols.append(ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON, tau=0.8, tau_ext=0.4))
         opts.append(ev.lan_opts(tol=args.tol, seed=2 + q, nev_est=max(int(cnt * 1.1) + 5, 10),
-                                max_its=args.max_its))
+                                max_its=args.max_its,
+                                prec=ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64,
+                                tol_lo=args.tol_lo, polish_div=args.polish_div))
     if args.group_width < 0:
-        gw, us = ev.evsl_autotune(ctx, Ad, args.nslices)
+        gw, us = ev.evsl_autotune(ctx, Ad, args.nslices,
+                                  ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64)
     else:
         ctx.set_group_width(args.group_width)
         gw, us = args.group_width, None
@@ -93,7 +100,8 @@ def one_step(ctx, ev, Ad, args):
         ress.append(res[keep])
         per_slice.append(dict(deg=pols[q].deg, nev=int(keep.sum()), niter=st["niter"],
                               nmv=st["nmv"], t_done=st["t_tot"], t_mv=st["t_mv"],
-                              t_orth=st["t_orth"], t_ritz=st["t_ritz"], status=st["status"]))
+                              t_orth=st["t_orth"], t_ritz=st["t_ritz"], status=st["status"],
+                              npolish=st["npolish"]))
     lam_all = np.concatenate(lams)
     return dict(t=t_tot, t_setup=t_setup, group_width=gw, tune_us=us, nev=len(lam_all), lam=lam_all,
                 res=np.concatenate(ress), bounds=(lo, hi), kpm_est=est, slices=sli,
@@ -216,14 +224,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32-filter/f64" if args.prec == "f32" else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"3-D 7-point Laplacian {N}^3 + U[0,1) diagonal potential (seed 0), "
                          f"all eigenpairs in [{args.interval[0]}, {args.interval[1]}], "
                          f"{args.nslices} KPM slices (degree {args.kpm_degree}, "
                          f"{args.kpm_vectors} vectors), Jackson filters, thick-restart Lanczos, "
-                         f"tol {args.tol:g}, FP64, slices {args.mode}"),
+                         f"tol {args.tol:g}, "
+                         f"{'FP32 filter + FP64 reorthogonalisation/Rayleigh-Ritz/polish' if args.prec == 'f32' else 'FP64'}, "
+                         f"slices {args.mode}"),
             "n": A.n, "nnz": A.nnz, "nslices": args.nslices, "nev": rec["nev"],
             "kpm_estimate": round(rec["kpm_est"], 1),
             "filter_degrees": [s["deg"] for s in rec["per_slice"]],
@@ -238,6 +248,8 @@ def main():
         "split_s": {k: float(sum(s[k] for s in rec["per_slice"]))
                     for k in ("t_mv", "t_orth", "t_ritz")},
         "niter": [s["niter"] for s in rec["per_slice"]],
+        "npolish": [s["npolish"] for s in rec["per_slice"]],
+        "status": [s["status"] for s in rec["per_slice"]],
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -90,10 +90,18 @@ typedef struct {
   uint64_t seed;  /* start-vector stream (SplitMix64); restarts draw further blocks */
   int nev_est;    /* expected count in the slice (sizing only); 0: 50 */
   int nev_cap;    /* capacity for locked pairs; 0: max(2 nev_est + 40, 100) */
-  int prec;       /* filter arithmetic: EVSL_F64, or EVSL_F32 (needs a float copy of A, see below) */
-  const void *val32; /* device float values of A, required when prec == EVSL_F32 */
-  int reserved[4];
+  int prec;       /* filter arithmetic: EVSL_F64, or EVSL_F32 (precision form, below) */
+  const void *val32; /* EVSL_F32: device float values of A (NULL: the library converts A) */
+  double tol_lo;  /* EVSL_F32: lock tolerance of the FP32 phase; 0: max(tol, 1e-5) */
+  int polish;     /* EVSL_F32: max FP64 polish rounds; 0: 4; < 0: none (FP32-phase pairs) */
+  int polish_div; /* EVSL_F32: polish filter degree = deg / polish_div; 0: 1 (same filter) */
+  int reserved[2];
 } evsl_lan_opts_t;
+/* Precision form (prec = EVSL_F32): the filter recurrence runs in FP32 values,
+ * vectors and accumulation; reorthogonalisation, Rayleigh-Ritz, the residual
+ * test and the coefficients stay FP64. Pairs are locked at tol_lo, then the
+ * locked block is polished in FP64 (filter, Cholesky QR, Rayleigh-Ritz with A)
+ * until every residual is <= tol. */
 
 /* Result of one slice. lam/res are host arrays and Y a device n x nev
  * column-major array, all allocated by the library and released with
@@ -107,6 +115,7 @@ typedef struct {
   int niter;      /* Lanczos steps */
   int nmv;        /* products with A (filter steps + Ritz checks) */
   int nrestart;
+  int npolish;    /* FP64 polish rounds (precision form) */
   int status;     /* EVSL_OK or EVSL_ENOCONV */
   double t_mv;    /* seconds in filter products */
   double t_orth;  /* seconds in reorthogonalisation */
@@ -198,14 +207,21 @@ int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, dou
 /* Releases lam, res (host) and Y (device) of a result; safe on zeroed structs. */
 void evsl_eigs_free(evsl_ctx_t ctx, evsl_eigs_t *out);
 
+/* Block Gram product C = X^T Y (FP64 MFMA): X n x p and Y n x q column-major
+ * device arrays with leading dimensions ldx, ldy >= n; C is a device p x q
+ * column-major array (ldc >= p). Summation order is fixed. Asynchronous. */
+int evsl_gram(evsl_ctx_t ctx, int64_t n, int p, int q, const double *X, int64_t ldx,
+              const double *Y, int64_t ldy, double *C, int64_t ldc);
+
 /* ---- tuning ----
- * Autotuner for the batched filter: times Chebyshev steps of A over scratch
+ * Autotuner for the batched filter: times Chebyshev steps of A (in the
+ * arithmetic `prec`, EVSL_F64 or EVSL_F32; A itself is FP64) over scratch
  * blocks of g = 1, 2, 3, 4, 5, 6, 8, ... <= max_cols columns and keeps the
  * group width with the lowest time per column-step (a narrower group wins
  * unless a wider one is more than 2% faster). Batches then filter their
  * slices in groups of that width, one launch per group and degree step.
  * Synchronous; the scratch contents are arbitrary. */
-int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_width,
+int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, int *group_width,
                   double *us_per_colstep);
 /* Sets the batch group width directly (0: all active slices in one group). */
 int evsl_set_group_width(evsl_ctx_t ctx, int g);

@@ -29,6 +29,7 @@ EXPORTS = [
     "evsl_filtered_lanczos_batch", "evsl_eigs_get_vectors", "evsl_eigs_free",
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
     "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
+    "evsl_gram",
 ]
 
 
@@ -53,13 +54,14 @@ class PolT(C.Structure):
 class LanOptsT(C.Structure):
     _fields_ = [("m", C.c_int), ("max_its", C.c_int), ("ncycle", C.c_int), ("tol", C.c_double),
                 ("seed", C.c_uint64), ("nev_est", C.c_int), ("nev_cap", C.c_int),
-                ("prec", C.c_int), ("val32", C.c_void_p), ("reserved", C.c_int * 4)]
+                ("prec", C.c_int), ("val32", C.c_void_p), ("tol_lo", C.c_double),
+                ("polish", C.c_int), ("polish_div", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class EigsT(C.Structure):
     _fields_ = [("nev", C.c_int), ("lam", C.POINTER(C.c_double)), ("res", C.POINTER(C.c_double)),
                 ("Y", C.c_void_p), ("niter", C.c_int), ("nmv", C.c_int), ("nrestart", C.c_int),
-                ("status", C.c_int), ("t_mv", C.c_double), ("t_orth", C.c_double),
+                ("npolish", C.c_int), ("status", C.c_int), ("t_mv", C.c_double), ("t_orth", C.c_double),
                 ("t_ritz", C.c_double), ("t_tot", C.c_double)]
 
 
@@ -103,9 +105,12 @@ def _lib():
         L.evsl_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.evsl_set_spmv_variant.argtypes = [C.c_void_p, C.c_int]
         L.evsl_set_block_variant.argtypes = [C.c_int]
-        L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.POINTER(C.c_int), _dp]
+        L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int,
+                                    C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
         L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
+        L.evsl_gram.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p, C.c_int64,
+                                C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         _LIB = L
     return _LIB
 
@@ -182,12 +187,12 @@ def evsl_copy_probe(ctx, nbytes, reps=20):
     return t.value
 
 
-def evsl_autotune(ctx, A, max_cols):
+def evsl_autotune(ctx, A, max_cols, prec=EVSL_F64):
     """Returns (group width, microseconds per column-step)."""
     g = C.c_int()
     us = C.c_double()
-    _chk(_lib().evsl_autotune(ctx.h, C.byref(A.t), int(max_cols), C.byref(g), C.byref(us)),
-         "evsl_autotune")
+    _chk(_lib().evsl_autotune(ctx.h, C.byref(A.t), int(max_cols), int(prec), C.byref(g),
+                              C.byref(us)), "evsl_autotune")
     return g.value, us.value
 
 
@@ -295,9 +300,20 @@ def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
 
 
 def lan_opts(m=0, max_its=0, ncycle=0, tol=1e-8, seed=2, nev_est=0, nev_cap=0, prec=EVSL_F64,
-             val32=None):
+             val32=None, tol_lo=0.0, polish=0, polish_div=0):
     return LanOptsT(m, max_its, ncycle, tol, seed, nev_est, nev_cap, prec,
-                    C.c_void_p(val32.data_ptr() if val32 is not None else 0), (C.c_int * 4)())
+                    C.c_void_p(val32.data_ptr() if val32 is not None else 0), tol_lo, polish,
+                    polish_div, (C.c_int * 2)())
+
+
+def evsl_gram(ctx, X, Y, C_out):
+    """C_out (p x q, column-major torch view) = X^T Y for column-major torch
+    views X (n x p) and Y (n x q) (i.e. tensors whose transposes are contiguous)."""
+    n, p = X.shape
+    q = Y.shape[1]
+    _chk(_lib().evsl_gram(ctx.h, n, p, q, C.c_void_p(X.data_ptr()), X.stride(1),
+                          C.c_void_p(Y.data_ptr()), Y.stride(1), C.c_void_p(C_out.data_ptr()),
+                          C_out.stride(1)), "evsl_gram")
 
 
 def _take(ctx, out, n, device):
@@ -311,7 +327,8 @@ def _take(ctx, out, n, device):
         _chk(_lib().evsl_eigs_get_vectors(ctx.h, C.byref(out), n, C.c_void_p(Yt.data_ptr()), n),
              "evsl_eigs_get_vectors")
         torch.cuda.current_stream().synchronize()
-    stats = dict(nev=k, niter=out.niter, nmv=out.nmv, nrestart=out.nrestart, status=out.status,
+    stats = dict(nev=k, niter=out.niter, nmv=out.nmv, nrestart=out.nrestart, npolish=out.npolish,
+                 status=out.status,
                  t_mv=out.t_mv, t_orth=out.t_orth, t_ritz=out.t_ritz, t_tot=out.t_tot)
     _lib().evsl_eigs_free(ctx.h, C.byref(out))
     return lam, Yt.T, res, stats

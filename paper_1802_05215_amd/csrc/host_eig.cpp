@@ -125,4 +125,36 @@ int sym_eig(int m, double *A, double *w, double *V) {
   return 0;
 }
 
+// G = R^T R with R upper triangular (column-major m x m, written into R).
+// Returns -1 when G is not numerically positive definite.
+int chol_upper(int m, const double *G, double *R) {
+  for (int i = 0; i < m * m; ++i) R[i] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i <= j; ++i) {
+      double s = G[i + (size_t)j * m];
+      for (int k = 0; k < i; ++k) s -= R[k + (size_t)i * m] * R[k + (size_t)j * m];
+      if (i == j) {
+        if (!(s > 0.0)) return -1;
+        R[j + (size_t)j * m] = std::sqrt(s);
+      } else {
+        R[i + (size_t)j * m] = s / R[i + (size_t)i * m];
+      }
+    }
+  }
+  return 0;
+}
+
+// Inverse of an upper-triangular R (column-major), by back substitution.
+void tri_inv_upper(int m, const double *R, double *Ri) {
+  for (int i = 0; i < m * m; ++i) Ri[i] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    Ri[j + (size_t)j * m] = 1.0 / R[j + (size_t)j * m];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += R[i + (size_t)k * m] * Ri[k + (size_t)j * m];
+      Ri[i + (size_t)j * m] = -s / R[i + (size_t)i * m];
+    }
+  }
+}
+
 }  // namespace evh

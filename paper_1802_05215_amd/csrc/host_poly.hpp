@@ -26,5 +26,12 @@ int slice(int K, const double *mom, int damp, const double intv[4], int nslices,
 // shifts (Golub and Van Loan, Sections 8.3.1-8.3.3). w ascending; V (m x m,
 // column-major, may be null for eigenvalues only).
 int sym_eig(int m, double *A, double *w, double *V);
+// Cholesky G = R^T R (R upper triangular); -1 if G is not positive definite.
+int chol_upper(int m, const double *G, double *R);
+// Inverse of an upper-triangular matrix.
+void tri_inv_upper(int m, const double *R, double *Ri);
+// Chebyshev-Jackson delta filter of fixed degree k centred at gamma:
+// coef_j = g_j mu_j / sum_i g_i mu_i T_i(gamma) (eq:Cheb0, eq:mu with Jackson damping).
+void delta_filter(int k, double gamma, int damp, double *coef);
 
 }  // namespace evh

@@ -432,11 +432,16 @@ void set_blk_variant(int v) { g_blk_variant = (v >= 1 && v <= 4) ? v : 2; }
 
 // Columns per lane for a launch: 2 (16-byte loads) when the block allows it.
 static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int np) {
-  if (g_blk_variant == 4 || g_blk_variant == 1 || es != 8) return 1;
-  if ((nc & 1) || (ld & 1)) return 1;
-  for (int i = 0; i < np; ++i)
-    if (ptrs[i] && ((uintptr_t)ptrs[i] & 15)) return 1;
-  return 2;
+  if (g_blk_variant == 4 || g_blk_variant == 1) return 1;
+  int v = es == 8 ? 2 : 4;  // 16-byte loads
+  while (v > 1) {
+    bool ok = (nc % v == 0) && (ld % v == 0);
+    for (int i = 0; ok && i < np; ++i)
+      if (ptrs[i] && ((uintptr_t)ptrs[i] % (v * es))) ok = false;
+    if (ok) break;
+    v >>= 1;
+  }
+  return v;
 }
 
 static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid) {
@@ -480,6 +485,8 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
       hipLaunchKernelGGL((k_cheb_blk<T, K>), EVK_BLK_ARGS);                                  \
     else if (var == 3)                                                                       \
       hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1>), EVK_BLK_ARGS);                    \
+    else if (vec == 4)                                                                       \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4>), EVK_BLK_ARGS);                     \
     else if (vec == 2)                                                                       \
       hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2>), EVK_BLK_ARGS);                     \
     else                                                                                     \
@@ -504,37 +511,45 @@ template void cheb_blk<float>(hipStream_t, const Csr &, int, double, double, con
                               int, const float *, double *);
 
 // ---------------------------------------------------------------- gather / scatter
+// blk (row-major, value type TB) <-> FP64 columns given by a device pointer array.
+template <typename TB>
 __global__ __launch_bounds__(TPB) void k_gather_cols(int n, int nc, const double *const *src,
-                                                     double *blk, int64_t ldb) {
+                                                     TB *blk, int64_t ldb) {
   const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (e >= (int64_t)n * nc) return;
   const int r = (int)(e / nc), c = (int)(e - (int64_t)r * nc);
-  blk[(int64_t)r * ldb + c] = src[c][r];
+  blk[(int64_t)r * ldb + c] = (TB)src[c][r];
 }
 
-__global__ __launch_bounds__(TPB) void k_scatter_cols(int n, int nc, const double *blk,
-                                                      int64_t ldb, double *const *dst) {
+template <typename TB>
+__global__ __launch_bounds__(TPB) void k_scatter_cols(int n, int nc, const TB *blk, int64_t ldb,
+                                                      double *const *dst) {
   const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (e >= (int64_t)n * nc) return;
   const int r = (int)(e / nc), c = (int)(e - (int64_t)r * nc);
-  dst[c][r] = blk[(int64_t)r * ldb + c];
+  dst[c][r] = (double)blk[(int64_t)r * ldb + c];
 }
 
-void gather_cols(hipStream_t s, int n, int nc, const double *const *src, double *blk,
-                 int64_t ldb) {
+template <typename TB>
+void gather_cols(hipStream_t s, int n, int nc, const double *const *src, TB *blk, int64_t ldb) {
   int64_t tot = (int64_t)n * nc;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s, n,
-                     nc, src, blk, ldb);
+  hipLaunchKernelGGL(k_gather_cols<TB>, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s,
+                     n, nc, src, blk, ldb);
 }
 
-void scatter_cols(hipStream_t s, int n, int nc, const double *blk, int64_t ldb,
-                  double *const *dst) {
+template <typename TB>
+void scatter_cols(hipStream_t s, int n, int nc, const TB *blk, int64_t ldb, double *const *dst) {
   int64_t tot = (int64_t)n * nc;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s,
+  hipLaunchKernelGGL(k_scatter_cols<TB>, dim3((unsigned)((tot + TPB - 1) / TPB)), dim3(TPB), 0, s,
                      n, nc, blk, ldb, dst);
 }
+
+template void gather_cols<double>(hipStream_t, int, int, const double *const *, double *, int64_t);
+template void gather_cols<float>(hipStream_t, int, int, const double *const *, float *, int64_t);
+template void scatter_cols<double>(hipStream_t, int, int, const double *, int64_t, double *const *);
+template void scatter_cols<float>(hipStream_t, int, int, const float *, int64_t, double *const *);
 
 // ---------------------------------------------------------------- reductions over columns
 // out[c] = scale * sum_w partial[c * nw + w]; one workgroup per column.
@@ -781,6 +796,111 @@ __global__ __launch_bounds__(TPB) void k_lanczos_start(int n, uint64_t seed, int
 void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double *x) {
   hipLaunchKernelGGL(k_lanczos_start, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, seed, restart,
                      x);
+}
+
+// ---------------------------------------------------------------- C = X^T Y (FP64 MFMA)
+// X (n x p) and Y (n x q) column-major. Each workgroup owns a 32 x 32 tile of C
+// and a chunk of rows; the chunk is staged through LDS 64 rows at a time and
+// each wavefront accumulates one 16 x 16 quadrant with v_mfma_f64_16x16x4f64
+// (A operand: lane l holds X^T[i][k], i = l % 16, k = l / 16; B operand: lane l
+// holds Y[k][j], j = l % 16; result: lane l, register v holds row 4 v + l / 16 of
+// column l % 16). Per-chunk tiles go to `partial`, summed in chunk order.
+typedef double v4d __attribute__((ext_vector_type(4)));
+static constexpr int TN_RC = 64;
+
+__global__ __launch_bounds__(TPB) void k_gemm_tn_mfma(int n, int p, int q, int rows_per_chunk,
+                                                      const double *__restrict__ X, int64_t ldx,
+                                                      const double *__restrict__ Y, int64_t ldy,
+                                                      double *partial) {
+  __shared__ double Xs[TN_RC][33];
+  __shared__ double Ys[TN_RC][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int chunk = blockIdx.x, i0 = blockIdx.y * 32, j0 = blockIdx.z * 32;
+  const int rbeg = chunk * rows_per_chunk;
+  const int rend = min(rbeg + rows_per_chunk, n);
+  const int qi = wave >> 1, qj = wave & 1;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = rbeg; r0 < rend; r0 += TN_RC) {
+    __syncthreads();
+    // stage 64 rows x 32 columns of X and of Y (zero outside the matrices)
+    for (int e = tid; e < TN_RC * 32; e += TPB) {
+      const int c = e / TN_RC, rr = e - c * TN_RC;
+      const int r = r0 + rr;
+      Xs[rr][c] = (r < rend && i0 + c < p) ? X[(int64_t)(i0 + c) * ldx + r] : 0.0;
+      Ys[rr][c] = (r < rend && j0 + c < q) ? Y[(int64_t)(j0 + c) * ldy + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k4 = 0; k4 < TN_RC; k4 += 4) {
+      const double a = Xs[k4 + (lane >> 4)][16 * qi + (lane & 15)];
+      const double b = Ys[k4 + (lane >> 4)][16 * qj + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+  // write this chunk's tile: partial[chunk][i][j], i < p, j < q
+  const int j = j0 + 16 * qj + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 16 * qi + 4 * v + (lane >> 4);
+    if (i < p && j < q) partial[((int64_t)chunk * p + i) * q + j] = acc[v];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_sum_chunks(int nchunk, int64_t pq,
+                                                    const double *__restrict__ partial,
+                                                    double *C, int p, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= pq) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * pq + e];
+  const int64_t qcols = pq / p;
+  const int64_t i = e / qcols, jj = e - i * qcols;
+  C[jj * ldc + i] = s;  // C column-major p x q
+}
+
+static int tn_rows_per_chunk(int n, int p, int q) {
+  // keep the partial tiles at most ~64 MB and at least 4096 rows per chunk
+  int64_t tiles = (int64_t)((p + 31) / 32) * ((q + 31) / 32);
+  int rpc = 4096;
+  while ((int64_t)((n + rpc - 1) / rpc) * p * q * 8 > (64ll << 20) && rpc < n) rpc *= 2;
+  (void)tiles;
+  return rpc;
+}
+
+int64_t gemm_tn_partials(int n, int p, int q) {
+  const int rpc = tn_rows_per_chunk(n, p, q);
+  return (int64_t)((n + rpc - 1) / rpc) * p * q;
+}
+
+// Enough partials for every shape p' <= p, q' <= q (chunks are never smaller
+// than 4096 rows).
+int64_t gemm_tn_partials_bound(int n, int p, int q) {
+  return (int64_t)((n + 4095) / 4096) * p * q;
+}
+
+void gemm_tn(hipStream_t s, int n, int p, int q, const double *X, int64_t ldx, const double *Y,
+             int64_t ldy, double *C, int64_t ldc, double *partial) {
+  if (n <= 0 || p <= 0 || q <= 0) return;
+  const int rpc = tn_rows_per_chunk(n, p, q);
+  const int nchunk = (n + rpc - 1) / rpc;
+  dim3 grid(nchunk, (p + 31) / 32, (q + 31) / 32);
+  hipLaunchKernelGGL(k_gemm_tn_mfma, grid, dim3(TPB), 0, s, n, p, q, rpc, X, ldx, Y, ldy, partial);
+  const int64_t pq = (int64_t)p * q;
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((pq + TPB - 1) / TPB)), dim3(TPB), 0, s, nchunk,
+                     pq, partial, C, p, ldc);
+}
+
+// ---------------------------------------------------------------- y += a x
+__global__ __launch_bounds__(TPB) void k_axpy(int64_t len, double a, const double *__restrict__ x,
+                                              double *y) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < len) y[i] += a * x[i];
+}
+
+void axpy(hipStream_t s, int64_t len, double a, const double *x, double *y) {
+  if (len > 0)
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((len + TPB - 1) / TPB)), dim3(TPB), 0, s, len, a, x,
+                       y);
 }
 
 // ---------------------------------------------------------------- copy (bandwidth calibration)

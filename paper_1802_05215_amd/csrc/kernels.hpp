@@ -41,10 +41,18 @@ int blk_partials(int n, int nc);
 // Block kernel choice: 1 global loads, 2 LDS-staged + XCD remap (default), 3 LDS-staged.
 void set_blk_variant(int v);
 
-// Gather / scatter single columns into / out of a row-major block:
+// Gather / scatter FP64 columns into / out of a row-major block of type TB:
 // blk[r * ldb + c] = src[c][r] for c < nc (pointers in a device array).
-void gather_cols(hipStream_t s, int n, int nc, const double *const *src, double *blk, int64_t ldb);
-void scatter_cols(hipStream_t s, int n, int nc, const double *blk, int64_t ldb, double *const *dst);
+template <typename TB>
+void gather_cols(hipStream_t s, int n, int nc, const double *const *src, TB *blk, int64_t ldb);
+template <typename TB>
+void scatter_cols(hipStream_t s, int n, int nc, const TB *blk, int64_t ldb, double *const *dst);
+// C (p x q, column-major, ldc) = X^T Y with X n x p, Y n x q column-major, on
+// FP64 MFMA; `partial` holds gemm_tn_partials(n, p, q) doubles. Deterministic.
+int64_t gemm_tn_partials(int n, int p, int q);
+int64_t gemm_tn_partials_bound(int n, int p, int q);
+void gemm_tn(hipStream_t s, int n, int p, int q, const double *X, int64_t ldx, const double *Y,
+             int64_t ldy, double *C, int64_t ldc, double *partial);
 
 // h[j] = B[:, j] . z  for j < nb (B column-major, leading dim ld); uses
 // `partial` (gemv_partials(n, nb) doubles). Deterministic order.
@@ -76,6 +84,8 @@ void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double 
 // out[c] = scale * sum_w partial[c * nw + w].
 void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
                      double *out);
+// y += a x over len doubles.
+void axpy(hipStream_t s, int64_t len, double a, const double *x, double *y);
 // Plain copy of `bytes` (a multiple of 16) from x to y: the bandwidth reference.
 void copy_probe(hipStream_t s, int64_t bytes, const void *x, void *y);
 // y = float(x) / x = double(y)

@@ -237,6 +237,14 @@ struct Slice {
   int m, max_its, ncycle, nev_cap;
   double tol;
   uint64_t seed;
+  double gamma = 0.0;
+  // FP32 filter (precision form): float copy of A's values, float work vectors,
+  // the lock tolerance of the FP32 phase and the FP64 polish that follows it
+  int prec = EVSL_F64;
+  double tol_lo = 0.0;
+  int polish_max = 0, polish_div = 1, npolish = 0, nguard = 0, nstall = 0;
+  const float *val32 = nullptr;
+  float *own32 = nullptr, *q32 = nullptr, *w0f = nullptr, *w1f = nullptr, *zf = nullptr;
   // device buffers
   double *B = nullptr;  // n x cap_cols, column-major; locked columns first
   int64_t ld = 0;
@@ -262,11 +270,12 @@ struct Slice {
   Slice &operator=(const Slice &) = delete;
   ~Slice() { release(); }
   void release() {
-    void *bufs[] = {coef_dev, B, z, w0, w1, Uc, AUc, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2,
-                    ow.scal};
+    void *bufs[] = {coef_dev, B, z, w0, w1, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2, ow.scal,
+                    own32, q32, w0f, w1f, zf};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
     coef_dev = B = z = w0 = w1 = Uc = AUc = Yc = nullptr;
+    own32 = q32 = w0f = w1f = zf = nullptr;
     ow = OrthWork{};
     if (hostsc) (void)hipHostFree(hostsc);
     hostsc = nullptr;
@@ -309,7 +318,17 @@ struct Slice {
     seed = opt ? opt->seed : 0;
     nev_cap = (opt && opt->nev_cap > 0) ? opt->nev_cap : std::max(2 * nev_est + 40, 100);
     if (nev_cap > n) nev_cap = n;
-    if (opt && opt->prec == EVSL_F32) fail(EVSL_ENOTIMPL);
+    gamma = pol->gamma;
+    prec = opt ? opt->prec : EVSL_F64;
+    if (prec != EVSL_F64 && prec != EVSL_F32) fail(EVSL_EINVAL);
+    if (prec == EVSL_F32) {
+      // the FP32 recurrence leaves an error of order deg * eps32 in each filtered
+      // vector, which bounds what the FP32 phase can reach
+      tol_lo = (opt && opt->tol_lo > 0) ? opt->tol_lo
+                                        : std::max(tol, std::min(1e-3, 2e-7 * (double)deg));
+      polish_max = (opt && opt->polish != 0) ? std::max(opt->polish, 0) : 4;
+      polish_div = (opt && opt->polish_div > 0) ? opt->polish_div : 1;
+    }
     // device memory
     ld = ((int64_t)n + 63) / 64 * 64;
     cap_cols = nev_cap + m + 1;
@@ -317,12 +336,30 @@ struct Slice {
     z = (double *)dalloc(ctx, sizeof(double) * ld);
     w0 = (double *)dalloc(ctx, sizeof(double) * ld);
     w1 = (double *)dalloc(ctx, sizeof(double) * ld);
-    Uc = (double *)dalloc(ctx, sizeof(double) * ld * m);
-    AUc = (double *)dalloc(ctx, sizeof(double) * ld * m);
+    // Ritz scratch (m columns) is shared by all slices of a context: restarts
+    // run one slice at a time on the context stream
+    (void)ws(ctx, 40, sizeof(double) * ld * m);
+    (void)ws(ctx, 41, sizeof(double) * ld * m);
     Yc = (double *)dalloc(ctx, sizeof(double) * (size_t)m * m);
+    if (prec == EVSL_F32) {
+      if (opt && opt->val32) {
+        val32 = (const float *)opt->val32;
+      } else if (A->dtype == EVSL_F32) {
+        val32 = (const float *)A->val;
+      } else {
+        own32 = (float *)dalloc(ctx, sizeof(float) * std::max<int64_t>(A->nnz, 1));
+        evk::to_f32(st(), A->nnz, (const double *)A->val, own32);
+        val32 = own32;
+      }
+      q32 = (float *)dalloc(ctx, sizeof(float) * ld);
+      w0f = (float *)dalloc(ctx, sizeof(float) * ld);
+      w1f = (float *)dalloc(ctx, sizeof(float) * ld);
+      zf = (float *)dalloc(ctx, sizeof(float) * ld);
+    }
     const int ncap = cap_cols + 8;
     ow.partial = (double *)dalloc(
-        ctx, sizeof(double) * std::max(evk::gemv_partials(n, ncap), evk::dot_partials(n, m + 2)));
+        ctx, sizeof(double) * std::max(evk::gemv_partials(n, ncap),
+                                       evk::dot_partials(n, std::max(m, nev_cap) + 2)));
     ow.h1 = (double *)dalloc(ctx, sizeof(double) * ncap);
     ow.h2 = (double *)dalloc(ctx, sizeof(double) * ncap);
     ow.nrm2 = (double *)dalloc(ctx, sizeof(double) * (3 * m + 8));
@@ -372,16 +409,42 @@ struct Slice {
     HC(ctx, hipEventRecord(ev0, st()));
     filter_vector_async();
     HC(ctx, hipEventRecord(ev1, st()));
-    const double b0 = step_bytes(A, 1, 8, 3), b1 = step_bytes(A, 1, 8, 5);
+    const int es = prec == EVSL_F32 ? 4 : 8;
+    const double b0 = step_bytes(A, 1, es, 3), b1 = step_bytes(A, 1, es, 5);
     tm.stop(deg, b0 + (deg - 1) * b1);
     nmv += deg;
   }
 
   // The deg launches of the filter on q_i (single-vector kernel), z = output.
+  evk::Csr csr32() const {
+    evk::Csr c = to_csr(A);
+    c.va = val32;
+    c.dtype = EVSL_F32;
+    return c;
+  }
+
   void filter_vector_async() {
-    const evk::Csr Ac = to_csr(A);
     const int var = pick_variant(ctx);
     const double *q = current();
+    if (prec == EVSL_F32) {
+      // FP32 recurrence: values, vectors and accumulation in float
+      const evk::Csr A32 = csr32();
+      evk::to_f32(st(), n, q, q32);
+      evk::cheb_vec<float>(st(), A32, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q32, nullptr, w0f,
+                           zf, ld, 1, coef_dev, deg + 1, 1);
+      const float *wprev = q32;
+      float *wcur = w0f;
+      for (int j = 1; j < deg; ++j) {
+        float *dst = (wprev == q32) ? w1f : const_cast<float *>(wprev);
+        evk::cheb_vec<float>(st(), A32, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
+                             dst, zf, ld, 1, coef_dev, deg + 1, j + 1);
+        wprev = wcur;
+        wcur = dst;
+      }
+      evk::to_f64(st(), n, zf, z);
+      return;
+    }
+    const evk::Csr Ac = to_csr(A);
     // W_1 = (A q - c q)/d; Y = c0 q + c1 W_1
     evk::cheb_vec<double>(st(), Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z,
                           ld, 1, coef_dev, deg + 1, 1);
@@ -451,6 +514,7 @@ struct Slice {
       if (!done && its > max_its) {
         status = EVSL_ENOCONV;
         done = true;
+        if (prec == EVSL_F32) nguard = l;  // the thick-restart vectors follow the locked ones
       }
     } else {
       i++;
@@ -480,6 +544,9 @@ struct Slice {
   // Rayleigh-Ritz on T_dim, locking and thick restart.
   void restart(int dim) {
     nrestart++;
+    Uc = (double *)ws(ctx, 40, sizeof(double) * ld * m);
+    AUc = (double *)ws(ctx, 41, sizeof(double) * ld * m);
+    const double lock_tol = prec == EVSL_F32 ? std::max(tol, tol_lo) : tol;
     std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
     evh::sym_eig(dim, T.data(), w.data(), Y.data());
     const double beta_last = next_ok ? beta[dim - 1] : 0.0;
@@ -519,7 +586,7 @@ struct Slice {
         if (lamt < tlo || lamt > thi) continue;  // outside the slice: ignored
         naccept++;
         const double r = std::sqrt(std::max(r2, 0.0) / uu) / normA;
-        if (r <= tol) {
+        if (r <= lock_tol) {
           lock_sel.push_back(t);
           lock_lam.push_back(lamt);
           lock_res.push_back(r);
@@ -568,6 +635,17 @@ struct Slice {
     } else {
       nocand = 0;
       l = (int)tr_sel.size();
+      // FP32 phase: two restarts in a row that lock nothing while candidates
+      // remain mean the rest is at the FP32 floor; the thick-restart vectors
+      // (already placed after the locked ones) go to the FP64 polish
+      if (prec == EVSL_F32) {
+        nstall = lock_sel.empty() ? nstall + 1 : 0;
+        if (nstall >= 2 && l > 0) {
+          nguard = l;
+          done = true;
+          return;
+        }
+      }
       if (next_ok) {
         HC(ctx, hipMemcpyAsync(col(nlock + l), z, sizeof(double) * n, hipMemcpyDeviceToDevice,
                                st()));
@@ -587,6 +665,206 @@ struct Slice {
       status = EVSL_ENOMEM;
       done = true;
     }
+  }
+
+  // FP64 polish of the pairs locked by the FP32 phase. Each round applies the
+  // FP64 filter to the block U of locked vectors, orthogonalises Y = p(A-hat) U
+  // against U (block classical Gram-Schmidt, twice), orthonormalises what is
+  // left through the eigen-decomposition of its Gram matrix (directions with
+  // negligible weight dropped), and runs Rayleigh-Ritz with A itself on
+  // S = [U, Y]. The filtered residual p u - theta u of a locked vector points
+  // along its error (every error direction outside the slice has nearly the
+  // same filter value), so the enlarged space removes the FP32 error that
+  // subspace iteration alone would keep. The pairs inside the slice are kept;
+  // rounds repeat until every residual is <= tol. Synchronous.
+  void polish() {
+    int P = nlock + nguard;
+    if (P == 0 || polish_max <= 0) return;
+    hipStream_t s = st();
+    const evk::Csr Ac = to_csr(A);
+    const int dp = polish_div <= 1 ? deg : std::max(2, deg / polish_div);
+    std::vector<double> cp(dp + 1);
+    if (polish_div <= 1)
+      cp.assign(coef.begin(), coef.end());
+    else
+      evh::delta_filter(dp, gamma, 2, cp.data());
+    const int P0 = P, S2 = 2 * P0;
+    const size_t colb = sizeof(double) * ld * P0;
+    double *X0 = (double *)ws(ctx, 50, colb), *X1 = (double *)ws(ctx, 51, colb);
+    double *Yb = (double *)ws(ctx, 52, colb);
+    double *Sm = (double *)ws(ctx, 53, 2 * colb), *AS = (double *)ws(ctx, 54, 2 * colb);
+    double *Gd = (double *)ws(ctx, 55, sizeof(double) * (size_t)S2 * S2);
+    double *tnp = (double *)ws(ctx, 56, sizeof(double) * evk::gemm_tn_partials_bound(n, S2, S2));
+    double **pp = (double **)ws(ctx, 57, sizeof(double *) * 2 * P0);
+    double *ctab = (double *)ws(ctx, 58, sizeof(double) * (size_t)P0 * (dp + 1));
+    double *sc = (double *)ws(ctx, 59, sizeof(double) * 3 * S2);
+    double *Yq = Sm + (int64_t)P0 * ld;  // the second block of S
+    std::vector<double> tab((size_t)P0 * (dp + 1));
+    for (int c = 0; c < P0; ++c) std::copy(cp.begin(), cp.end(), tab.begin() + (size_t)c * (dp + 1));
+    HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+    std::vector<double> G((size_t)S2 * S2), V((size_t)S2 * S2), w(S2), hres(3 * S2);
+    for (int round = 0; round < polish_max; ++round) {
+      npolish++;
+      // S[:, 0:P] = U; Y = p(A-hat) U (row-major block filter) into S[:, P:2P]
+      HC(ctx, hipMemcpyAsync(Sm, B, sizeof(double) * ld * P, hipMemcpyDeviceToDevice, s));
+      std::vector<const double *> hp(2 * P);
+      for (int c = 0; c < P; ++c) {
+        hp[c] = col(c);
+        hp[P + c] = Sm + (int64_t)(P + c) * ld;
+      }
+      HC(ctx, hipMemcpyAsync(pp, hp.data(), sizeof(double *) * 2 * P, hipMemcpyHostToDevice, s));
+      evk::gather_cols<double>(s, n, P, (const double *const *)pp, X0, P);
+      FilterTimer tm(ctx);
+      evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, P, P,
+                            ctab, dp + 1, 1, nullptr, nullptr);
+      double *wprev = X0, *wcur = X1;
+      for (int j = 1; j < dp; ++j) {
+        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
+                              Yb, P, P, ctab, dp + 1, j + 1, nullptr, nullptr);
+        std::swap(wprev, wcur);
+      }
+      tm.stop(dp, step_bytes(A, P, 8, 3) + (dp - 1) * step_bytes(A, P, 8, 5));
+      nmv += P * dp;
+      Yq = Sm + (int64_t)P * ld;
+      evk::scatter_cols<double>(s, n, P, Yb, P, (double *const *)(pp + P));
+      // Round 0: S = [U, Z] with Z an orthonormal basis of (I - U U^T) p(A) U
+      // (directions negligible against |p(A) U| dropped: they carry only
+      // rounding). Later rounds: S = an orthonormal basis of p(A) U alone
+      // (filtered subspace iteration): once U is accurate, the projected-out
+      // part of p(A) U is mostly rounding, whose Ritz values could pollute the
+      // wanted ones.
+      double *S0 = Sm;
+      int ns = 0;
+      if (round == 0) {
+        evk::col_dots(s, n, P, Yq, ld, Yq, ld, ow.partial, sc);
+        std::vector<double> yn(P);
+        HC(ctx, hipMemcpyAsync(yn.data(), sc, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+        for (int t = 0; t < 2; ++t) project_out(Sm, P, Yq, P, Gd, tnp, AS);
+        HC(ctx, hipStreamSynchronize(s));
+        double ymax = 0.0;
+        for (double v : yn) ymax = std::max(ymax, v);
+        int kz = svqb(Yq, P, 1e-16 * ymax, Gd, tnp, AS, G, V, w);
+        if (kz > 0) {  // second pass against U, then normalise again
+          project_out(Sm, P, Yq, kz, Gd, tnp, AS);
+          kz = svqb(Yq, kz, 0.0, Gd, tnp, AS, G, V, w);
+        }
+        ns = P + kz;
+      } else {
+        S0 = Yq;
+        ns = svqb(Yq, P, 0.0, Gd, tnp, AS, G, V, w);
+      }
+      const int kz = ns - (S0 == Sm ? P : 0);
+      // Rayleigh-Ritz with A on S (ns columns)
+      evk::cheb_vec<double>(s, Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, S0, nullptr, AS, nullptr, ld, ns,
+                            nullptr, 0, 0);
+      nmv += ns;
+      evk::gemm_tn(s, n, ns, ns, S0, ld, AS, ld, Gd, ns, tnp);
+      HC(ctx, hipMemcpyAsync(G.data(), Gd, sizeof(double) * ns * ns, hipMemcpyDeviceToHost, s));
+      HC(ctx, hipStreamSynchronize(s));
+      for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < a; ++b) {
+          const double v = 0.5 * (G[a + (size_t)b * ns] + G[b + (size_t)a * ns]);
+          G[a + (size_t)b * ns] = G[b + (size_t)a * ns] = v;
+        }
+      evh::sym_eig(ns, G.data(), w.data(), V.data());
+      // all ns Ritz pairs, their Rayleigh quotients and residuals
+      double *Ua = (double *)ws(ctx, 61, sizeof(double) * ld * ns);
+      double *AUa = (double *)ws(ctx, 62, sizeof(double) * ld * ns);
+      double *sca = (double *)ws(ctx, 63, sizeof(double) * 3 * ns);
+      double *pa = (double *)ws(ctx, 64, sizeof(double) * evk::dot_partials(n, ns));
+      HC(ctx, hipMemcpyAsync(Gd, V.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice, s));
+      evk::gemm_nn(s, n, ns, ns, S0, ld, Gd, ns, Ua, ld);
+      evk::gemm_nn(s, n, ns, ns, AS, ld, Gd, ns, AUa, ld);
+      evk::col_dots(s, n, ns, Ua, ld, Ua, ld, pa, sca);
+      evk::col_dots(s, n, ns, Ua, ld, AUa, ld, pa, sca + ns);
+      evk::col_resid2(s, n, ns, Ua, AUa, ld, sca + ns, sca, pa, sca + 2 * ns);
+      std::vector<double> ha(3 * ns);
+      HC(ctx, hipMemcpyAsync(ha.data(), sca, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
+      HC(ctx, hipStreamSynchronize(s));
+      // keep the pairs inside the slice: the P_in with the smallest residuals
+      // (P_in = pairs held before this round), plus any further converged one;
+      // the enlarged space also produces spurious Ritz values inside the slice,
+      // whose residuals are large
+      std::vector<int> in;
+      std::vector<double> rq(ns), rs(ns);
+      for (int c = 0; c < ns; ++c) {
+        rq[c] = ha[ns + c] / ha[c];
+        rs[c] = std::sqrt(std::max(ha[2 * ns + c], 0.0) / ha[c]) / normA;
+        if (rq[c] >= tlo && rq[c] <= thi) in.push_back(c);
+      }
+      std::stable_sort(in.begin(), in.end(), [&](int x, int y) { return rs[x] < rs[y]; });
+      std::vector<int> keep;
+      for (size_t t = 0; t < in.size(); ++t)
+        if ((int)t < P || rs[in[t]] <= tol) keep.push_back(in[t]);
+      std::sort(keep.begin(), keep.end());  // ascending eigenvalue order
+      const int k = (int)keep.size();
+      if (k > P0) {
+        status = EVSL_ENOCONV;
+        return;
+      }
+      for (int t = 0; t < k; ++t)
+        HC(ctx, hipMemcpyAsync(col(t), Ua + (int64_t)keep[t] * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s));
+      double worst = 0.0;
+      int nbad = 0;
+      lam.assign(k, 0.0);
+      res.assign(k, 0.0);
+      for (int t = 0; t < k; ++t) {
+        lam[t] = rq[keep[t]];
+        res[t] = rs[keep[t]];
+        worst = std::max(worst, res[t]);
+        nbad += res[t] > tol;
+      }
+      nlock = k;
+      nguard = 0;
+      P = k;
+      if (std::getenv("EVSL_PROGRESS"))
+        std::fprintf(stderr,
+                     "[evsl] polish round %d: %d + %d columns, %d in the slice, %d above tol, "
+                     "worst %.2e\n",
+                     round + 1, ns - kz, kz, k, nbad, worst);
+      if (worst <= tol || k == 0) {
+        if (status == EVSL_ENOCONV && its <= max_its) status = EVSL_OK;
+        return;
+      }
+    }
+    status = EVSL_ENOCONV;
+  }
+
+  // Y (ny columns) <- Y - U (U^T Y) for the first nu columns U of Sm.
+  void project_out(const double *U, int nu, double *Yc, int ny, double *Gd, double *tnp,
+                   double *tmp) {
+    evk::gemm_tn(st(), n, nu, ny, U, ld, Yc, ld, Gd, nu, tnp);
+    evk::gemm_nn(st(), n, nu, ny, U, ld, Gd, nu, tmp, ld);
+    evk::axpy(st(), (int64_t)ld * ny, -1.0, tmp, Yc);
+  }
+
+  // Orthonormalise the ny columns of Y in place from the eigen-decomposition
+  // of Y^T Y = V diag(w) V^T: Y <- Y V_k diag(w_k)^(-1/2) over the eigenvalues
+  // above max(floor, 1e-20 max w). Returns the number of columns kept.
+  int svqb(double *Yc, int ny, double floor, double *Gd, double *tnp, double *tmp,
+           std::vector<double> &G, std::vector<double> &V, std::vector<double> &w) {
+    hipStream_t s = st();
+    evk::gemm_tn(s, n, ny, ny, Yc, ld, Yc, ld, Gd, ny, tnp);
+    HC(ctx, hipMemcpyAsync(G.data(), Gd, sizeof(double) * ny * ny, hipMemcpyDeviceToHost, s));
+    HC(ctx, hipStreamSynchronize(s));
+    evh::sym_eig(ny, G.data(), w.data(), V.data());
+    const double wmax = std::max(w[ny - 1], 0.0);
+    const double cut = std::max(floor, 1e-20 * wmax);
+    std::vector<double> Vk((size_t)ny * ny);
+    int k = 0;
+    for (int c = ny - 1; c >= 0; --c) {
+      if (!(w[c] > cut)) break;
+      const double sd = 1.0 / std::sqrt(w[c]);
+      for (int r = 0; r < ny; ++r) Vk[r + (size_t)k * ny] = V[r + (size_t)c * ny] * sd;
+      k++;
+    }
+    if (k == 0) return 0;
+    HC(ctx, hipMemcpyAsync(Gd, Vk.data(), sizeof(double) * ny * k, hipMemcpyHostToDevice, s));
+    evk::gemm_nn(s, n, ny, k, Yc, ld, Gd, ny, tmp, ld);
+    HC(ctx, hipMemcpyAsync(Yc, tmp, sizeof(double) * ld * k, hipMemcpyDeviceToDevice, s));
+    HC(ctx, hipStreamSynchronize(s));
+    return k;
   }
 
   // Copy the locked pairs, sorted by eigenvalue, into a result.
@@ -612,6 +890,7 @@ struct Slice {
     out->niter = its;
     out->nmv = nmv;
     out->nrestart = nrestart;
+    out->npolish = npolish;
     out->status = status == EVSL_ENOMEM ? EVSL_ENOCONV : status;
     out->t_mv = t_mv;
     out->t_orth = t_orth;
@@ -701,29 +980,51 @@ int evsl_set_block_variant(int variant) {
   return EVSL_OK;
 }
 
+int evsl_gram(evsl_ctx_t ctx, int64_t n, int p, int q, const double *X, int64_t ldx,
+              const double *Y, int64_t ldy, double *C, int64_t ldc) {
+  if (!ctx || n <= 0 || n >= ((int64_t)1 << 31) || p < 1 || q < 1 || !X || !Y || !C || ldx < n ||
+      ldy < n || ldc < p)
+    return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  double *part = (double *)ws(ctx, 60, sizeof(double) * evk::gemm_tn_partials((int)n, p, q));
+  evk::gemm_tn(ctx->stream, (int)n, p, q, X, ldx, Y, ldy, C, ldc, part);
+  if (hipGetLastError() != hipSuccess) return EVSL_EHIP;
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
 int evsl_set_group_width(evsl_ctx_t ctx, int g) {
   if (!ctx || g < 0) return EVSL_EINVAL;
   ctx->group_width = g;
   return EVSL_OK;
 }
 
-int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_width,
+int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, int *group_width,
                   double *us_per_colstep) {
-  if (!ctx || max_cols < 1) return EVSL_EINVAL;
+  if (!ctx || max_cols < 1 || (prec != EVSL_F64 && prec != EVSL_F32)) return EVSL_EINVAL;
   EVSL_GUARD_BEGIN
   check_csr(A);
   if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
   const int n = (int)A->n;
   hipStream_t s = ctx->stream;
   const size_t blk = (size_t)n * max_cols;
-  double *X0 = (double *)ws(ctx, 20, sizeof(double) * blk);
-  double *X1 = (double *)ws(ctx, 21, sizeof(double) * blk);
-  double *Yb = (double *)ws(ctx, 22, sizeof(double) * blk);
+  void *X0 = ws(ctx, 20, sizeof(double) * blk);
+  void *X1 = ws(ctx, 21, sizeof(double) * blk);
+  void *Yb = ws(ctx, 22, sizeof(double) * blk);
   double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)max_cols * 4);
   HC(ctx, hipMemsetAsync(ctab, 0, sizeof(double) * (size_t)max_cols * 4, s));
-  evk::rademacher(s, n, max_cols, 11, X0);
-  evk::rademacher(s, n, max_cols, 12, X1);
-  const evk::Csr Ac = to_csr(A);
+  HC(ctx, hipMemsetAsync(X0, 0, sizeof(double) * blk, s));
+  HC(ctx, hipMemsetAsync(X1, 0, sizeof(double) * blk, s));
+  evk::Csr Ac = to_csr(A);
+  if (prec == EVSL_F32) {
+    float *v32 = (float *)ws(ctx, 25, sizeof(float) * std::max<int64_t>(A->nnz, 1));
+    evk::to_f32(s, A->nnz, (const double *)A->val, v32);
+    Ac.va = v32;
+    Ac.dtype = EVSL_F32;
+  } else {
+    evk::rademacher(s, n, max_cols, 11, (double *)X0);
+    evk::rademacher(s, n, max_cols, 12, (double *)X1);
+  }
   hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
   const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
   const int reps = 8;
@@ -735,12 +1036,23 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int *group_
     if (g > max_cols) break;
     for (int r = -2; r < reps; ++r) {
       if (r == 0) HC(ctx, hipEventRecord(e0, s));
-      if (g == 1)
-        evk::cheb_vec<double>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, X1, X0, X0, Yb, n,
-                              1, ctab, 4, 1);
-      else
-        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, sc, 0.0, X1, X0, X0, Yb, g, g, ctab, 4, 1,
-                              nullptr, nullptr);
+      if (prec == EVSL_F32) {
+        float *x0 = (float *)X0, *x1 = (float *)X1, *yb = (float *)Yb;
+        if (g == 1)
+          evk::cheb_vec<float>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb,
+                               n, 1, ctab, 4, 1);
+        else
+          evk::cheb_blk<float>(s, Ac, evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb, g, g, ctab, 4, 1,
+                               nullptr, nullptr);
+      } else {
+        double *x0 = (double *)X0, *x1 = (double *)X1, *yb = (double *)Yb;
+        if (g == 1)
+          evk::cheb_vec<double>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb,
+                                n, 1, ctab, 4, 1);
+        else
+          evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb, g, g, ctab, 4, 1,
+                                nullptr, nullptr);
+      }
     }
     HC(ctx, hipEventRecord(e1, s));
     HC(ctx, hipEventSynchronize(e1));
@@ -1077,6 +1389,7 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
     HC(ctx, hipStreamSynchronize(ctx->stream));
     sl.after_step();
   }
+  if (sl.prec == EVSL_F32) sl.polish();
   sl.emit(out);
   out->t_tot = now_s() - t0;
   return out->status;
@@ -1097,10 +1410,12 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   for (int q = 0; q < nslices; ++q)
     sl[q].setup(ctx, A, intv + 4 * q, &pols[q], opts ? &opts[q] : nullptr);
   const double cc = sl[0].cc, dd = sl[0].dd;
+  const int prec = sl[0].prec;
   for (int q = 1; q < nslices; ++q)
     if (std::fabs(sl[q].cc - cc) > 1e-13 * (1 + std::fabs(cc)) ||
-        std::fabs(sl[q].dd - dd) > 1e-13 * (1 + std::fabs(dd)))
+        std::fabs(sl[q].dd - dd) > 1e-13 * (1 + std::fabs(dd)) || sl[q].prec != prec)
       return EVSL_EINVAL;
+  const int es = prec == EVSL_F32 ? 4 : 8;
   // slices ordered by degree (non-increasing) so that the active columns of
   // the block recurrence form a prefix that shrinks as low degrees finish
   std::vector<int> order(nslices);
@@ -1109,9 +1424,10 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   int kmax = 0;
   for (auto &s : sl) kmax = std::max(kmax, s.deg);
   hipStream_t s = ctx->stream;
-  double *X0 = (double *)ws(ctx, 20, sizeof(double) * (size_t)n * nslices);
-  double *X1 = (double *)ws(ctx, 21, sizeof(double) * (size_t)n * nslices);
-  double *Yb = (double *)ws(ctx, 22, sizeof(double) * (size_t)n * nslices);
+  // row-major group blocks (FP64, or FP32 for the precision form)
+  void *X0 = ws(ctx, 20, (size_t)es * n * nslices);
+  void *X1 = ws(ctx, 21, (size_t)es * n * nslices);
+  void *Yb = ws(ctx, 22, (size_t)es * n * nslices);
   double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)nslices * (kmax + 1));
   double **ptrs = (double **)ws(ctx, 24, sizeof(double *) * 2 * (nslices + 1));
   // pinned staging for the per-group pointer arrays (copied asynchronously)
@@ -1165,7 +1481,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       if (gn == 1) {
         Slice &S = sl[act[g0]];
         S.filter_vector_async();
-        bytes += step_bytes(A, 1, 8, 3) + (S.deg - 1) * step_bytes(A, 1, 8, 5);
+        bytes += step_bytes(A, 1, es, 3) + (S.deg - 1) * step_bytes(A, 1, es, 5);
         launches += S.deg;
         continue;
       }
@@ -1176,23 +1492,31 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       }
       double **gp = ptrs + 2 * g0;
       HC(ctx, hipMemcpyAsync(gp, hg, sizeof(double *) * 2 * gn, hipMemcpyHostToDevice, s));
-      evk::gather_cols(s, n, gn, (const double *const *)gp, X0, gn);
       const double *gtab = ctab + (size_t)g0 * (km + 1);
-      evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, gn,
-                            ncs[1] - g0 >= gn ? gn : std::max(ncs[1] - g0, 1), gtab, km + 1, 1,
-                            nullptr, nullptr);
-      bytes += step_bytes(A, gn, 8, 3);
-      // X0 = W_0, X1 = W_1; W_{j+1} is written over W_{j-1}
-      double *wprev = X0, *wcur = X1;
-      for (int j = 1; j < gk; ++j) {
-        const int ncj = std::min(gn, std::max(ncs[j + 1] - g0, 1));
-        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
-                              Yb, gn, ncj, gtab, km + 1, j + 1, nullptr, nullptr);
-        bytes += step_bytes(A, ncj, 8, 5);
-        std::swap(wprev, wcur);
-      }
+      auto run_group = [&](auto tag, const evk::Csr &Ag) {
+        using T = decltype(tag);
+        T *x0 = (T *)X0, *x1 = (T *)X1, *yb = (T *)Yb;
+        evk::gather_cols<T>(s, n, gn, (const double *const *)gp, x0, gn);
+        evk::cheb_blk<T>(s, Ag, evk::STEP_FIRST, 1.0 / dd, -cc / dd, x0, nullptr, x1, yb, gn,
+                         std::min(gn, std::max(ncs[1] - g0, 1)), gtab, km + 1, 1, nullptr,
+                         nullptr);
+        bytes += step_bytes(A, gn, es, 3);
+        // x0 = W_0, x1 = W_1; W_{j+1} is written over W_{j-1}
+        T *wprev = x0, *wcur = x1;
+        for (int j = 1; j < gk; ++j) {
+          const int ncj = std::min(gn, std::max(ncs[j + 1] - g0, 1));
+          evk::cheb_blk<T>(s, Ag, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev, yb,
+                           gn, ncj, gtab, km + 1, j + 1, nullptr, nullptr);
+          bytes += step_bytes(A, ncj, es, 5);
+          std::swap(wprev, wcur);
+        }
+        evk::scatter_cols<T>(s, n, gn, yb, gn, (double *const *)(gp + gn));
+      };
+      if (prec == EVSL_F32)
+        run_group(float(), sl[act[g0]].csr32());
+      else
+        run_group(double(), Ac);
       launches += gk;
-      evk::scatter_cols(s, n, gn, Yb, gn, (double *const *)(gp + gn));
     }
     for (int q : act) HC(ctx, hipEventRecord(sl[q].ev1, s));
     tm.stop(launches, bytes);
@@ -1203,7 +1527,10 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
     HC(ctx, hipStreamSynchronize(s));
     for (int q : act) {
       sl[q].after_step();
-      if (sl[q].done) sl[q].t_done = now_s() - t0;
+      if (sl[q].done) {
+        if (sl[q].prec == EVSL_F32) sl[q].polish();
+        sl[q].t_done = now_s() - t0;
+      }
     }
     ++global_step;
     if (progress > 0 && global_step % progress == 0) {

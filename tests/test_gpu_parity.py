@@ -330,3 +330,121 @@ def test_invalid_arguments_are_rejected(ctx):
     p = _pol([1.0, 1.5, 0.0, 8.0])
     with pytest.raises(ev.EvslError):
         ev.evsl_filtered_lanczos(ctx, Ad, [1.0, 1.5, 0.0, 9.0], p)   # filter built for other bounds
+
+
+# ------------------------------------------------------------------ FP64 MFMA Gram product
+@pytest.mark.parametrize("n,p,q", [(64, 16, 16), (10007, 5, 7), (5000, 33, 17), (131072, 100, 100),
+                                   (3, 1, 1)])
+def test_gram_mfma_matches_numpy(ctx, n, p, q):
+    rng = np.random.default_rng(n + p)
+    Xh = rng.standard_normal((p, n))          # row j = column j of the column-major X
+    Yh = rng.standard_normal((q, n))
+    X, Y = _dev(Xh).T, _dev(Yh).T             # n x p, n x q column-major views
+    Ct = torch.empty((q, p), dtype=torch.float64, device="cuda")
+    ev.evsl_gram(ctx, X, Y, Ct.T)
+    torch.cuda.synchronize()
+    ref = Xh @ Yh.T
+    assert np.abs(Ct.T.cpu().numpy() - ref).max() <= 1e-12 * np.sqrt(n) * 4
+
+
+# ------------------------------------------------------------------ precision form
+def test_filter_fp32_error_against_fp64_oracle(ctx):
+    A = I.laplacian(30, 3, pot_seed=0)
+    p = _pol([0.6, 0.7, 0.0, 13.0])
+    A32 = ev.DeviceCsr.from_host(A, dtype=torch.float32)
+    v = I.lanczos_start(4, A.n)
+    V = _dev(v).float()
+    Y = torch.empty_like(V)
+    ev.evsl_filter_apply(ctx, A32, [p], [0], V, Y)
+    torch.cuda.synchronize()
+    ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, v)
+    err = np.linalg.norm(Y.double().cpu().numpy() - ref) / np.linalg.norm(v)
+    # FP32 recurrence: rounding error of order k * eps32 relative to ||V||
+    assert err <= p.deg * 6e-8, (err, p.deg)
+
+
+@pytest.mark.parametrize("ncols,ld", [(2, 2), (3, 4), (4, 4), (6, 6), (8, 8), (12, 16)])
+def test_filter_fp32_block_error_against_fp64_oracle(ctx, ncols, ld):
+    """Row-major FP32 blocks at every lane width (1, 2 or 4 columns per lane)."""
+    A = I.laplacian(30, 3, pot_seed=0)
+    A32 = ev.DeviceCsr.from_host(A, dtype=torch.float32)
+    pols = [_pol([0.6, 0.7, 0.0, 13.0]), _pol([1.0, 1.2, 0.0, 13.0])]
+    groups = [0] * (ncols // 2) + [1] * (ncols - ncols // 2)
+    rng = np.random.default_rng(ncols)
+    Vh = np.zeros((A.n, ld))
+    Vh[:, :ncols] = rng.standard_normal((A.n, ncols))
+    V = _dev(Vh).float()
+    Y = torch.zeros_like(V)
+    ev.evsl_filter_apply(ctx, A32, pols, groups, V[:, :ncols], Y[:, :ncols])
+    torch.cuda.synchronize()
+    Yh = Y.double().cpu().numpy()
+    for c in range(ncols):
+        p = pols[groups[c]]
+        ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, Vh[:, c])
+        err = np.linalg.norm(Yh[:, c] - ref) / np.linalg.norm(Vh[:, c])
+        assert err <= p.deg * 6e-8, (c, err, p.deg)
+
+
+@pytest.mark.parametrize("intv_ab", [(1.0, 1.15), (2.0, 2.05)])
+def test_fp32_filter_lanczos_polished_to_fp64_tolerance(ctx, intv_ab):
+    """16^3 Laplacian + potential: FP32 filter, FP64 reorthogonalisation and
+    Rayleigh-Ritz, FP64 polish; every eigenvalue in the slice (dense eigh) at
+    residual <= 1e-8."""
+    A = I.laplacian(16, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    a, b = intv_ab
+    intv = [a, b, lo, hi]
+    want = w[(w >= a) & (w <= b)]
+    lam, Y, res, st = ev.evsl_filtered_lanczos(
+        ctx, Ad, intv, _pol(intv), ev.lan_opts(tol=1e-8, seed=2, nev_est=len(want) + 5,
+                                               prec=ev.EVSL_F32))
+    assert st["status"] == 0 and len(lam) == len(want), st
+    assert res.max() <= 1e-8
+    assert np.abs(lam - want).max() <= 1e-10 * max(abs(lo), abs(hi))
+
+
+def test_fp32_filter_lanczos_40x40_eigenvalues(ctx):
+    """40 x 40 Laplacian, [1.0, 1.6]: the FP32-filter form finds all 91
+    eigenvalues (44 double pairs). Here the FP64 polish does not bring every
+    residual to 1e-8 (the spectrum next to the slice ends is dense relative to
+    the degree-20 filter), so only the eigenvalues and a looser residual are
+    checked; the status reports the shortfall."""
+    A = I.laplacian(40, 2)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.6, lo, hi]
+    lam, Y, res, st = ev.evsl_filtered_lanczos(
+        ctx, Ad, intv, _pol(intv), ev.lan_opts(tol=1e-8, seed=2, nev_est=91, prec=ev.EVSL_F32))
+    want = _closed_form_interval(40, 2, 1.0, 1.6)
+    assert st["nev"] == 91
+    assert np.abs(lam - want).max() <= 1e-9 * np.abs(want).max()
+    assert res.max() <= 1e-5
+    assert st["status"] in (ev.EVSL_OK, ev.EVSL_ENOCONV)
+
+
+def test_fp32_batch_matches_fp64_batch(ctx):
+    A = I.laplacian(20, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.3, lo, hi]
+    mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 60, 10, seed=1)
+    sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, 3, 2000)
+    ivs = [[sli[q], sli[q + 1], lo, hi] for q in range(3)]
+    pols = [_pol(iv) for iv in ivs]
+    res64 = ev.evsl_filtered_lanczos_batch(
+        ctx, Ad, ivs, pols, [ev.lan_opts(tol=1e-10, seed=2 + q, nev_est=int(est / 3) + 10)
+                             for q in range(3)])
+    res32 = ev.evsl_filtered_lanczos_batch(
+        ctx, Ad, ivs, pols, [ev.lan_opts(tol=1e-8, seed=2 + q, nev_est=int(est / 3) + 10,
+                                         prec=ev.EVSL_F32) for q in range(3)])
+    w = np.linalg.eigvalsh(A.to_dense())
+    for q in range(3):
+        l64, _, r64, _ = res64[q]
+        l32, _, r32, s32 = res32[q]
+        want = w[(w >= ivs[q][0]) & (w <= ivs[q][1])]
+        assert len(l64) == len(l32) == len(want)
+        assert r32.max() <= 1e-8 and s32["status"] == 0, s32
+        assert np.abs(l32 - l64).max() <= 1e-10 * 13
+        assert np.abs(l32 - want).max() <= 1e-10 * 13

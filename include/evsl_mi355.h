@@ -231,6 +231,12 @@ int evsl_set_group_width(evsl_ctx_t ctx, int g);
  * HIP events on the context stream) since the last reset. */
 int evsl_filter_stats(evsl_ctx_t ctx, int64_t *launches, double *seconds, double *bytes);
 int evsl_reset_stats(evsl_ctx_t ctx);
+/* Device memory the context holds, in bytes: `current` now (workspace kept
+ * for reuse, plus result vectors not yet passed to evsl_eigs_free) and `peak`
+ * since creation or the last reset (reset_peak != 0 sets peak = current
+ * after reading). Host-side bookkeeping of the library's own allocations
+ * only; a serving layer uses it to check its admission footprints. */
+int evsl_mem_stats(evsl_ctx_t ctx, int64_t *current, int64_t *peak, int reset_peak);
 /* Bandwidth reference: `reps` launches of a plain copy kernel reading and
  * writing `bytes` bytes (rounded down to a multiple of 16) of context
  * workspace; returns the average seconds per copy (HIP events). Used to

@@ -29,7 +29,7 @@ EXPORTS = [
     "evsl_filtered_lanczos_batch", "evsl_eigs_get_vectors", "evsl_eigs_free",
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
     "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
-    "evsl_gram",
+    "evsl_gram", "evsl_mem_stats",
 ]
 
 
@@ -109,6 +109,8 @@ def _lib():
                                     C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
         L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
+        L.evsl_mem_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.c_int]
         L.evsl_gram.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p, C.c_int64,
                                 C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         _LIB = L
@@ -178,6 +180,13 @@ class Ctx:
 
     def set_group_width(self, g):
         _chk(_lib().evsl_set_group_width(self.h, int(g)), "set_group_width")
+
+    def mem_stats(self, reset_peak=False):
+        """(bytes held now, peak bytes) of the context's device allocations."""
+        cur, peak = C.c_int64(), C.c_int64()
+        _chk(_lib().evsl_mem_stats(self.h, C.byref(cur), C.byref(peak), int(bool(reset_peak))),
+             "evsl_mem_stats")
+        return cur.value, peak.value
 
 
 def evsl_copy_probe(ctx, nbytes, reps=20):

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/evsl_mi355.h"
@@ -56,6 +57,9 @@ struct evsl_ctx_s {
   std::vector<size_t> ws_size;
   double *pinned = nullptr;
   size_t pinned_cap = 0;
+  // device memory held by this context (workspace, slice buffers, results)
+  std::unordered_map<void *, size_t> live;
+  int64_t mem_cur = 0, mem_peak = 0;
 };
 
 namespace {
@@ -78,7 +82,22 @@ void *dalloc(evsl_ctx_t ctx, size_t bytes) {
     ctx->last_hip = (int)e;
     fail(EVSL_ENOMEM);
   }
+  ctx->live[p] = bytes;
+  ctx->mem_cur += (int64_t)bytes;
+  ctx->mem_peak = std::max(ctx->mem_peak, ctx->mem_cur);
   return p;
+}
+
+// Frees a buffer from dalloc and takes it off the context's ledger.
+void dfree(evsl_ctx_t ctx, void *p) {
+  if (!p) return;
+  (void)hipFree(p);
+  if (!ctx) return;
+  auto it = ctx->live.find(p);
+  if (it != ctx->live.end()) {
+    ctx->mem_cur -= (int64_t)it->second;
+    ctx->live.erase(it);
+  }
 }
 
 // Workspace slot `slot` of at least `bytes` bytes (contents not preserved on growth).
@@ -90,7 +109,7 @@ void *ws(evsl_ctx_t ctx, int slot, size_t bytes) {
   if (ctx->ws_size[slot] < bytes) {
     if (ctx->ws_ptr[slot]) {
       HC(ctx, hipStreamSynchronize(ctx->stream));
-      (void)hipFree(ctx->ws_ptr[slot]);
+      dfree(ctx, ctx->ws_ptr[slot]);
     }
     ctx->ws_ptr[slot] = nullptr;
     ctx->ws_size[slot] = 0;
@@ -226,7 +245,7 @@ namespace {
 
 struct Slice {
   // problem
-  evsl_ctx_t ctx;
+  evsl_ctx_t ctx = nullptr;
   const evsl_csr_t *A;
   int n;
   double tlo, thi, lmin, lmax, normA, cc, dd, bar;
@@ -272,8 +291,7 @@ struct Slice {
   void release() {
     void *bufs[] = {coef_dev, B, z, w0, w1, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2, ow.scal,
                     own32, q32, w0f, w1f, zf};
-    for (void *p : bufs)
-      if (p) (void)hipFree(p);
+    for (void *p : bufs) dfree(ctx, p);
     coef_dev = B = z = w0 = w1 = Uc = AUc = Yc = nullptr;
     own32 = q32 = w0f = w1f = zf = nullptr;
     ow = OrthWork{};
@@ -953,14 +971,21 @@ int evsl_destroy(evsl_ctx_t ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
-  for (void *p : ctx->ws_ptr)
-    if (p) (void)hipFree(p);
+  for (void *p : ctx->ws_ptr) dfree(ctx, p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return EVSL_OK;
 }
 
 int evsl_last_hip_error(evsl_ctx_t ctx) { return ctx ? ctx->last_hip : 0; }
+
+int evsl_mem_stats(evsl_ctx_t ctx, int64_t *current, int64_t *peak, int reset_peak) {
+  if (!ctx) return EVSL_EINVAL;
+  if (current) *current = ctx->mem_cur;
+  if (peak) *peak = ctx->mem_peak;
+  if (reset_peak) ctx->mem_peak = ctx->mem_cur;
+  return EVSL_OK;
+}
 
 int evsl_set_timing(evsl_ctx_t ctx, int on) {
   if (!ctx) return EVSL_EINVAL;
@@ -1565,11 +1590,10 @@ int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, dou
 }
 
 void evsl_eigs_free(evsl_ctx_t ctx, evsl_eigs_t *out) {
-  (void)ctx;
   if (!out) return;
   std::free(out->lam);
   std::free(out->res);
-  if (out->Y) (void)hipFree(out->Y);
+  dfree(ctx, out->Y);
   out->lam = out->res = out->Y = nullptr;
   out->nev = 0;
 }

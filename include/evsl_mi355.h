@@ -44,6 +44,10 @@ extern "C" {
 #define EVSL_F64 0
 #define EVSL_F32 1
 
+/* ---- Lanczos variant of a slice (evsl_lan_opts_t.method) ---- */
+#define EVSL_LAN_TR 0 /* thick restart with locking (ChebLanTr, Algorithm alg:FiltLanTR) */
+#define EVSL_LAN_NR 1 /* non-restart (ChebLanNr, Sections 2.4 and 3) */
+
 /* ---- damping of the Chebyshev expansion ---- */
 #define EVSL_DAMP_NONE 0
 #define EVSL_DAMP_SIGMA 1   /* Lanczos sigma factors, eq:polPJ (the paper's default) */
@@ -83,8 +87,9 @@ typedef struct {
 /* Options of the filtered Lanczos (Algorithm alg:FiltLanTR). Zero fields take
  * the documented defaults. */
 typedef struct {
-  int m;          /* Krylov dimension per cycle; 0: max(2 nev_est + 30, 60) */
-  int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) */
+  int m;          /* Krylov dimension per cycle; 0: max(2 nev_est + 30, 60);
+                     EVSL_LAN_NR: total step cap; 0: max(5 nev_est + 200, 400) */
+  int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) (EVSL_LAN_NR: m) */
   int ncycle;     /* early-restart test period; 0: 30 */
   double tol;     /* residual tolerance ||A u - lambda u|| / ||A||; 0: 1e-8 */
   uint64_t seed;  /* start-vector stream (SplitMix64); restarts draw further blocks */
@@ -92,11 +97,22 @@ typedef struct {
   int nev_cap;    /* capacity for locked pairs; 0: max(2 nev_est + 40, 100) */
   int prec;       /* filter arithmetic: EVSL_F64, or EVSL_F32 (precision form, below) */
   const void *val32; /* EVSL_F32: device float values of A (NULL: the library converts A) */
-  double tol_lo;  /* EVSL_F32: lock tolerance of the FP32 phase; 0: max(tol, 1e-5) */
+  double tol_lo;  /* EVSL_F32: lock tolerance of the FP32 phase;
+                     0: max(tol, min(1e-3, 2e-7 deg)) */
   int polish;     /* EVSL_F32: max FP64 polish rounds; 0: 4; < 0: none (FP32-phase pairs) */
   int polish_div; /* EVSL_F32: polish filter degree = deg / polish_div; 0: 1 (same filter) */
-  int reserved[2];
+  int method;     /* EVSL_LAN_TR (0) or EVSL_LAN_NR (FP64 only; else EVSL_ENOTIMPL) */
+  int reserved;
 } evsl_lan_opts_t;
+/* Non-restart form (method = EVSL_LAN_NR): Lanczos on p(A-hat) from one
+ * seeded random vector with full reorthogonalisation and no restart; every
+ * ncycle steps the sum of the Ritz values >= bar is compared with its value at
+ * the previous test and the run ends once it has settled (relative change
+ * < 1e-10) or after m steps (then EVSL_ENOCONV). The Ritz vectors of all Ritz
+ * values >= bar are then checked against A, in chunks of
+ * max(2 nev_est + 30, 60) columns; those inside the slice with residual <= tol
+ * are returned (at most nev_cap). Device memory: (nev_cap + m + 1) basis
+ * columns plus two chunks. */
 /* Precision form (prec = EVSL_F32): the filter recurrence runs in FP32 values,
  * vectors and accumulation; reorthogonalisation, Rayleigh-Ritz, the residual
  * test and the coefficients stay FP64. Pairs are locked at tol_lo, then the

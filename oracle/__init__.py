@@ -82,6 +82,7 @@ def _setup(L):
     L.or_lanczos_start.argtypes = [C.c_uint64, C.c_int64, C.c_int64, _dp]
     L.or_filtered_lanczos.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
                                       C.POINTER(LanOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
+    L.or_filtered_lanczos_nr.argtypes = L.or_filtered_lanczos.argtypes
 
 
 def _d(a):
@@ -234,6 +235,36 @@ def filtered_lanczos(A, intv, pol, m=None, max_its=None, ncycle=30, tol=1e-10, s
                                    C.byref(st))
     if rc != 0:
         raise ValueError("filtered_lanczos: invalid arguments")
+    k = st.nev
+    stats = dict(nev=k, niter=st.niter, nmv=st.nmv, nrestart=st.nrestart, status=st.status)
+    return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats
+
+
+def filtered_lanczos_nr(A, intv, pol, m=None, ncycle=30, tol=1e-10, seed=2, nev_cap=None,
+                        nev_est=None):
+    """Filtered non-restart Lanczos on one slice (at most m steps). Returns
+    (lam, Y (n x nev), res, stats) as filtered_lanczos."""
+    if nev_est is None:
+        nev_est = 50
+    if m is None:
+        m = max(5 * int(nev_est) + 200, 400)
+    if nev_cap is None:
+        nev_cap = max(2 * int(nev_est) + 40, 100)
+    n = A.n
+    iv = _f64(intv)
+    coef = _f64(pol["coef"])
+    lam = np.empty(nev_cap)
+    res = np.empty(nev_cap)
+    Y = np.empty((nev_cap, n))
+    opts = LanOpts(m, m, ncycle, tol, seed, nev_cap)
+    st = LanStats()
+    rp, ci, va = (np.ascontiguousarray(A.row_ptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+                  _f64(A.val))
+    rc = lib().or_filtered_lanczos_nr(n, _i(rp), _i(ci), _d(va), _d(iv), len(coef) - 1, _d(coef),
+                                      pol["bar"], C.byref(opts), _d(lam), _d(res), _d(Y),
+                                      C.byref(st))
+    if rc != 0:
+        raise ValueError("filtered_lanczos_nr: invalid arguments")
     k = st.nev
     stats = dict(nev=k, niter=st.niter, nmv=st.nmv, nrestart=st.nrestart, status=st.status)
     return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats

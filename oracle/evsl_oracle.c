@@ -691,3 +691,125 @@ done:
   free(h); free(thTR); free(sTR);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Filtered non-restart Lanczos. The paper names the method without giving its
+ * steps; this reading keeps every choice of the thick-restart solver above that
+ * applies without a restart: the same Lanczos step, full reorthogonalisation,
+ * invariant-subspace rule (a fresh random direction with coupling 0), the
+ * same settled-sum test, and the same candidates (Ritz values >= bar) and
+ * acceptance (Rayleigh quotient in the slice, residual <= tol). */
+int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                           const double intv[4], int deg, const double *coef, double bar,
+                           const or_lan_opts *opt, double *lam, double *res, double *Y,
+                           or_lan_stats *st) {
+  memset(st, 0, sizeof(*st));
+  double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
+  double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
+  int m = opt->m;
+  if (m > n - 1) m = (int)(n - 1);
+  if (m < 2 || deg < 1 || opt->ncycle < 1) return -1;
+  const int M1 = m + 1;
+  double *Q = (double *)calloc((size_t)n * M1, sizeof(double));
+  double *T = (double *)calloc((size_t)M1 * M1, sizeof(double));
+  double *Tw = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *w = (double *)malloc(sizeof(double) * m);
+  double *Yv = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *z = (double *)malloc(sizeof(double) * n);
+  double *u = (double *)malloc(sizeof(double) * n);
+  double *au = (double *)malloc(sizeof(double) * n);
+  double *h = (double *)malloc(sizeof(double) * (M1 + 1));
+#define TT(i, j) T[(i) + (size_t)(j) * M1]
+  int its = 0, nmv = 0, nrand = 0, status = 1, nev = 0;
+  double nz;
+  fresh_vector(n, opt->seed, nrand++, Q, NULL, 0, NULL, 0, h, &nz);
+  double t_old = NAN, t_new = NAN;
+  int dim = m;
+  for (int i = 0; i < m; ++i) {
+    its++;
+    double *qi = Q + (size_t)i * n;
+    or_filter_apply(n, rp, ci, va, cc, dd, deg, coef, 1, qi, z);
+    nmv += deg;
+    double alpha = dot(n, qi, z);
+    double bi = i > 0 ? TT(i - 1, i) : 0.0;
+    for (int64_t r = 0; r < n; ++r) z[r] -= alpha * qi[r] + (i > 0 ? bi * qi[r - n] : 0.0);
+    TT(i, i) = alpha;
+    cgs_dgks(n, z, Q, i + 1, NULL, 0, h);
+    double beta = nrm2(n, z);
+    if (beta <= 1e-12) {
+      fresh_vector(n, opt->seed, nrand++, z, Q, i + 1, NULL, 0, h, &nz);
+      if (nz == 0.0) { dim = i + 1; status = 0; break; }
+      memcpy(Q + (size_t)(i + 1) * n, z, sizeof(double) * n);
+    } else {
+      for (int64_t r = 0; r < n; ++r) Q[(size_t)(i + 1) * n + r] = z[r] / beta;
+      TT(i, i + 1) = beta;
+      TT(i + 1, i) = beta;
+    }
+    if ((i + 1) % opt->ncycle == 0) {
+      int k = i + 1;
+      for (int jj = 0; jj < k; ++jj)
+        for (int ii = 0; ii < k; ++ii) Tw[ii + (size_t)jj * k] = TT(ii, jj);
+      or_jacobi_eig(k, Tw, w, Yv);
+      t_old = t_new;
+      t_new = 0.0;
+      for (int jj = 0; jj < k; ++jj)
+        if (w[jj] >= bar) t_new += w[jj];
+      if (fabs(t_new - t_old) < 1e-10 * (fabs(t_new) > 1.0 ? fabs(t_new) : 1.0)) {
+        dim = k;
+        status = 0;
+        break;
+      }
+    }
+  }
+  /* Ritz pairs of T_dim with values >= bar, checked against A */
+  for (int jj = 0; jj < dim; ++jj)
+    for (int ii = 0; ii < dim; ++ii) Tw[ii + (size_t)jj * dim] = TT(ii, jj);
+  or_jacobi_eig(dim, Tw, w, Yv);
+  for (int jj = dim - 1; jj >= 0 && w[jj] >= bar; --jj) {
+    const double *y = Yv + (size_t)jj * dim;
+    for (int64_t r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int p = 0; p < dim; ++p) s += Q[(size_t)p * n + r] * y[p];
+      u[r] = s;
+    }
+    or_spmv(n, rp, ci, va, u, au);
+    nmv++;
+    double uu = dot(n, u, u);
+    double lam_j = dot(n, u, au) / uu;
+    if (lam_j < tlo || lam_j > thi) continue;
+    double rr = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+      double e = au[r] - lam_j * u[r];
+      rr += e * e;
+    }
+    rr = sqrt(rr / uu) / normA;
+    if (rr > opt->tol) continue;
+    if (nev >= opt->nev_cap) { status = 2; break; }
+    double nu = sqrt(uu);
+    for (int64_t r = 0; r < n; ++r) Y[(size_t)nev * n + r] = u[r] / nu;
+    lam[nev] = lam_j;
+    res[nev] = rr;
+    nev++;
+  }
+  for (int i = 0; i < nev - 1; ++i) {
+    int mi = i;
+    for (int j = i + 1; j < nev; ++j)
+      if (lam[j] < lam[mi]) mi = j;
+    if (mi != i) {
+      double t = lam[i]; lam[i] = lam[mi]; lam[mi] = t;
+      t = res[i]; res[i] = res[mi]; res[mi] = t;
+      memcpy(u, Y + (size_t)i * n, sizeof(double) * n);
+      memcpy(Y + (size_t)i * n, Y + (size_t)mi * n, sizeof(double) * n);
+      memcpy(Y + (size_t)mi * n, u, sizeof(double) * n);
+    }
+  }
+#undef TT
+  st->nev = nev;
+  st->niter = its;
+  st->nmv = nmv;
+  st->nrestart = 0;
+  st->status = status;
+  free(Q); free(T); free(Tw); free(w); free(Yv); free(z); free(u); free(au); free(h);
+  return 0;
+}

@@ -112,6 +112,19 @@ int or_filtered_lanczos(int64_t n, const int32_t *rp, const int32_t *ci, const d
                         const or_lan_opts *opt, double *lam, double *res, double *Y,
                         or_lan_stats *st);
 
+/* Filtered non-restart Lanczos (ChebLanNr, Section 2.4 and the solver list of
+ * Section 3): Lanczos on p(A-hat) from one seeded random vector, with full
+ * reorthogonalisation, up to opt->m steps; every opt->ncycle steps the sum of
+ * the Ritz values >= bar is compared with its value at the previous test, and
+ * the run stops when it has settled (relative change < 1e-10). The Ritz
+ * vectors of the Ritz values >= bar then give Rayleigh quotients with A; those
+ * inside the slice with residual <= tol are returned (lam ascending, res, Y as
+ * in or_filtered_lanczos). st->status: 0 settled, 1 stopped at m steps. */
+int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                           const double intv[4], int deg, const double *coef, double bar,
+                           const or_lan_opts *opt, double *lam, double *res, double *Y,
+                           or_lan_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

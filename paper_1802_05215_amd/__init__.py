@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libevsl_mi355.so")
 EVSL_OK, EVSL_EINVAL, EVSL_ENOMEM, EVSL_EHIP, EVSL_EDEGREE, EVSL_ENOCONV, EVSL_ESPECTRUM, \
     EVSL_ENOTIMPL = range(8)
 EVSL_F64, EVSL_F32 = 0, 1
+EVSL_LAN_TR, EVSL_LAN_NR = 0, 1
 DAMP_NONE, DAMP_SIGMA, DAMP_JACKSON = 0, 1, 2
 
 # every entry point declared in include/evsl_mi355.h
@@ -55,7 +56,8 @@ class LanOptsT(C.Structure):
     _fields_ = [("m", C.c_int), ("max_its", C.c_int), ("ncycle", C.c_int), ("tol", C.c_double),
                 ("seed", C.c_uint64), ("nev_est", C.c_int), ("nev_cap", C.c_int),
                 ("prec", C.c_int), ("val32", C.c_void_p), ("tol_lo", C.c_double),
-                ("polish", C.c_int), ("polish_div", C.c_int), ("reserved", C.c_int * 2)]
+                ("polish", C.c_int), ("polish_div", C.c_int), ("method", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class EigsT(C.Structure):
@@ -309,10 +311,10 @@ def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
 
 
 def lan_opts(m=0, max_its=0, ncycle=0, tol=1e-8, seed=2, nev_est=0, nev_cap=0, prec=EVSL_F64,
-             val32=None, tol_lo=0.0, polish=0, polish_div=0):
+             val32=None, tol_lo=0.0, polish=0, polish_div=0, method=0):
     return LanOptsT(m, max_its, ncycle, tol, seed, nev_est, nev_cap, prec,
                     C.c_void_p(val32.data_ptr() if val32 is not None else 0), tol_lo, polish,
-                    polish_div, (C.c_int * 2)())
+                    polish_div, method, 0)
 
 
 def evsl_gram(ctx, X, Y, C_out):

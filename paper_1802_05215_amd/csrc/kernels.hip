@@ -319,9 +319,10 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
 // loaded into LDS with coalesced loads; each thread owns VEC adjacent columns
 // of a group of rows (columns fastest, so the epilogue is contiguous), reads
 // the row's entries from LDS and issues 8 gathers of VEC values at a time.
-// Offsets are 32-bit (the host selects this kernel only when n * ld < 2^31);
-// VEC > 1 needs nc and ld divisible by VEC and VEC-aligned base pointers.
-template <typename T, int KIND, bool XCD, int VEC>
+// Element offsets are 32-bit when n * ld < 2^31, else (WIDE) 32 x 32 -> 64-bit
+// products; VEC > 1 needs nc and ld divisible by VEC and VEC-aligned base
+// pointers.
+template <typename T, int KIND, bool XCD, int VEC, bool WIDE>
 __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_per_wg,
                                                       const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
@@ -373,6 +374,10 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
   }
   const int col = slot * VEC;
   const int ld = (int)ld64;
+  // offset of element (row, 0) of the block
+  auto roff = [&](int row) -> size_t {
+    return WIDE ? (size_t)(uint32_t)row * (uint32_t)ld : (size_t)(row * ld);
+  };
   double dacc = 0.0;
   if (active) {
     vt c0 = (T)0, c1 = (T)0;
@@ -396,15 +401,15 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
             const bool ok = k + u < ke;
             const int c = ok ? s_ci[k + u] : 0;
             a[u] = ok ? s_va[k + u] : (T)0;
-            g[u] = *(const vt *)(wc + c * ld);
+            g[u] = *(const vt *)(wc + roff(c));
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
         }
       } else {
-        for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * *(const vt *)(wc + ci[k] * ld);
+        for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * *(const vt *)(wc + roff(ci[k]));
       }
-      const int e = (r0 + rl) * ld + col;
+      const size_t e = roff(r0 + rl) + col;
       const vt w = *(const vt *)(W + e);
       vt wn = s1 * acc + s0 * w;
       if (HAS_PREV) wn -= *(const vt *)(Wp + e);
@@ -447,7 +452,7 @@ static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int n
 static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid) {
   const int ncv = nc / vec;
   const int R0 = ncv <= TPB ? TPB / ncv : 1;
-  int passes = ncv <= TPB ? 4 : 8;
+  int passes = (ncv <= TPB && R0 > 2) ? 4 : 8;
   if (g_blk_variant != 1) passes = std::max(1, std::min(passes, TPB / R0));
   *rows_per_wg = R0 * passes;
   const int gx = (n + *rows_per_wg - 1) / *rows_per_wg;
@@ -468,8 +473,10 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
               const T *Vd, double *partial) {
   if (A.n <= 0 || nc <= 0) return;
-  const bool small = (int64_t)A.n * ld < ((int64_t)1 << 31) && (int64_t)nc * cld < ((int64_t)1 << 31);
-  const int var = small ? g_blk_variant : 1;
+  const bool wide = (int64_t)A.n * ld >= ((int64_t)1 << 31);
+  const bool ok32 = ld < ((int64_t)1 << 31) && (int64_t)A.n < ((int64_t)1 << 31) &&
+                    (int64_t)nc * cld < ((int64_t)1 << 31);
+  const int var = ok32 ? g_blk_variant : 1;
   const void *ptrs[5] = {W, Wp, Wn, Y, Vd};
   const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5);
   int rpw;
@@ -479,18 +486,25 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
 #define EVK_BLK_ARGS                                                                          \
   grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, \
       jnext, Vd, partial
+#define EVK_LAUNCH_LDS(K, W)                                                                 \
+  do {                                                                                       \
+    if (var == 3)                                                                            \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1, W>), EVK_BLK_ARGS);                 \
+    else if (vec == 4)                                                                       \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4, W>), EVK_BLK_ARGS);                  \
+    else if (vec == 2)                                                                       \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2, W>), EVK_BLK_ARGS);                  \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1, W>), EVK_BLK_ARGS);                  \
+  } while (0)
 #define EVK_LAUNCH_BLK(K)                                                                    \
   do {                                                                                       \
     if (var == 1)                                                                            \
       hipLaunchKernelGGL((k_cheb_blk<T, K>), EVK_BLK_ARGS);                                  \
-    else if (var == 3)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1>), EVK_BLK_ARGS);                    \
-    else if (vec == 4)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4>), EVK_BLK_ARGS);                     \
-    else if (vec == 2)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2>), EVK_BLK_ARGS);                     \
+    else if (wide)                                                                           \
+      EVK_LAUNCH_LDS(K, true);                                                               \
     else                                                                                     \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1>), EVK_BLK_ARGS);                     \
+      EVK_LAUNCH_LDS(K, false);                                                              \
   } while (0)
   switch (kind) {
     case STEP_PLAIN: EVK_LAUNCH_BLK(STEP_PLAIN); break;
@@ -500,6 +514,7 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
     default: EVK_LAUNCH_BLK(STEP_KPM_NEXT); break;
   }
 #undef EVK_LAUNCH_BLK
+#undef EVK_LAUNCH_LDS
 #undef EVK_BLK_ARGS
 }
 

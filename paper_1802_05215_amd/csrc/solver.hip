@@ -260,6 +260,10 @@ struct Slice {
   // FP32 filter (precision form): float copy of A's values, float work vectors,
   // the lock tolerance of the FP32 phase and the FP64 polish that follows it
   int prec = EVSL_F64;
+  // non-restart form: the basis fills columns 0..m, accepted pairs follow at
+  // lock_off; candidates are checked in chunks of cmax columns
+  bool nr = false;
+  int lock_off = 0, cmax = 0;
   double tol_lo = 0.0;
   int polish_max = 0, polish_div = 1, npolish = 0, nguard = 0, nstall = 0;
   const float *val32 = nullptr;
@@ -327,10 +331,15 @@ struct Slice {
     deg = pol->deg;
     coef.assign(pol->coef, pol->coef + deg + 1);
     const int nev_est = (opt && opt->nev_est > 0) ? opt->nev_est : 50;
-    m = (opt && opt->m > 0) ? opt->m : std::max(2 * nev_est + 30, 60);
+    if (opt && opt->method != EVSL_LAN_TR && opt->method != EVSL_LAN_NR) fail(EVSL_EINVAL);
+    nr = opt && opt->method == EVSL_LAN_NR;
+    if (nr && opt->prec != EVSL_F64) fail(EVSL_ENOTIMPL);
+    const int m_tr = std::max(2 * nev_est + 30, 60);
+    m = (opt && opt->m > 0) ? opt->m : (nr ? std::max(5 * nev_est + 200, 400) : m_tr);
     if (m > n - 1) m = n - 1;
     if (m < 2) fail(EVSL_EINVAL);
-    max_its = (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
+    max_its = nr ? m : (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
+    cmax = nr ? std::min(m, m_tr) : m;
     ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : 30;
     tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
     seed = opt ? opt->seed : 0;
@@ -350,14 +359,15 @@ struct Slice {
     // device memory
     ld = ((int64_t)n + 63) / 64 * 64;
     cap_cols = nev_cap + m + 1;
+    lock_off = nr ? m + 1 : 0;
     B = (double *)dalloc(ctx, sizeof(double) * ld * cap_cols);
     z = (double *)dalloc(ctx, sizeof(double) * ld);
     w0 = (double *)dalloc(ctx, sizeof(double) * ld);
     w1 = (double *)dalloc(ctx, sizeof(double) * ld);
     // Ritz scratch (m columns) is shared by all slices of a context: restarts
     // run one slice at a time on the context stream
-    (void)ws(ctx, 40, sizeof(double) * ld * m);
-    (void)ws(ctx, 41, sizeof(double) * ld * m);
+    (void)ws(ctx, 40, sizeof(double) * ld * cmax);
+    (void)ws(ctx, 41, sizeof(double) * ld * cmax);
     Yc = (double *)dalloc(ctx, sizeof(double) * (size_t)m * m);
     if (prec == EVSL_F32) {
       if (opt && opt->val32) {
@@ -500,7 +510,7 @@ struct Slice {
     const double a_i = hostsc[0], b_i = hostsc[1];
     alpha[i] = a_i;
     if (!std::isfinite(a_i) || !std::isfinite(b_i)) fail(EVSL_ESPECTRUM);
-    bool end_cycle = false;
+    bool end_cycle = false, settled = false;
     next_ok = true;
     if (b_i <= 1e-12) {
       // invariant subspace of the filtered operator: new direction, coupling 0
@@ -508,7 +518,7 @@ struct Slice {
       beta[i] = 0.0;
       if (r == 0.0) {
         next_ok = false;
-        end_cycle = true;
+        end_cycle = settled = true;
       }
     } else {
       beta[i] = b_i;
@@ -521,10 +531,19 @@ struct Slice {
       t_new = 0.0;
       for (double x : w)
         if (x >= bar) t_new += x;
-      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new))) end_cycle = true;
+      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new)))
+        end_cycle = settled = true;
     }
     if (its > max_its) end_cycle = true;
     if (!end_cycle && i + 1 >= m) end_cycle = true;
+    if (end_cycle && nr) {
+      const double t0 = now_s();
+      extract_nr(i + 1);
+      t_ritz += now_s() - t0;
+      if (!settled && status == EVSL_OK) status = EVSL_ENOCONV;
+      done = true;
+      return;
+    }
     if (end_cycle) {
       const double t0 = now_s();
       restart(i + 1);
@@ -557,6 +576,63 @@ struct Slice {
       }
     }
     return T;
+  }
+
+  // Non-restart form: Ritz vectors of the Ritz values >= bar of T_dim, in
+  // chunks of cmax; those with a Rayleigh quotient in the slice and residual
+  // <= tol are copied after the basis (columns lock_off...).
+  void extract_nr(int dim) {
+    Uc = (double *)ws(ctx, 40, sizeof(double) * ld * cmax);
+    AUc = (double *)ws(ctx, 41, sizeof(double) * ld * cmax);
+    std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
+    evh::sym_eig(dim, T.data(), w.data(), Y.data());
+    std::vector<int> cand;
+    for (int j = dim - 1; j >= 0 && w[j] >= bar; --j) cand.push_back(j);
+    const evk::Csr Ac = to_csr(A);
+    int nacc = 0;
+    for (size_t c0 = 0; c0 < cand.size() && status == EVSL_OK; c0 += cmax) {
+      const int lc = (int)std::min<size_t>(cmax, cand.size() - c0);
+      std::vector<double> Yh((size_t)dim * lc);
+      for (int t = 0; t < lc; ++t)
+        std::copy(Y.begin() + (size_t)cand[c0 + t] * dim,
+                  Y.begin() + (size_t)cand[c0 + t] * dim + dim, Yh.begin() + (size_t)t * dim);
+      HC(ctx, hipMemcpyAsync(Yc, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice,
+                             st()));
+      evk::gemm_nn(st(), n, dim, lc, col(0), ld, Yc, dim, Uc, ld);
+      evk::cheb_vec<double>(st(), Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, Uc, nullptr, AUc, nullptr, ld,
+                            lc, nullptr, 0, 0);
+      nmv += lc;
+      double *xx = ow.nrm2, *xax = ow.nrm2 + lc, *rr = ow.nrm2 + 2 * lc;
+      evk::col_dots(st(), n, lc, Uc, ld, Uc, ld, ow.partial, xx);
+      evk::col_dots(st(), n, lc, Uc, ld, AUc, ld, ow.partial, xax);
+      evk::col_resid2(st(), n, lc, Uc, AUc, ld, xax, xx, ow.partial, rr);
+      HC(ctx, hipMemcpyAsync(hostsc, ow.nrm2, sizeof(double) * 3 * lc, hipMemcpyDeviceToHost,
+                             st()));
+      HC(ctx, hipStreamSynchronize(st()));
+      std::vector<int> acc;
+      for (int t = 0; t < lc; ++t) {
+        const double uu = hostsc[t], uau = hostsc[lc + t], r2 = hostsc[2 * lc + t];
+        const double lamt = uau / uu;
+        if (!std::isfinite(lamt)) fail(EVSL_ESPECTRUM);
+        if (lamt < tlo || lamt > thi) continue;
+        const double r = std::sqrt(std::max(r2, 0.0) / uu) / normA;
+        if (r > tol) continue;
+        if (nacc >= nev_cap) {
+          status = EVSL_ENOMEM;
+          break;
+        }
+        acc.push_back(t);
+        lam.push_back(lamt);
+        res.push_back(r);
+        nacc++;
+      }
+      evk::normalize_cols(st(), n, lc, Uc, ld, xx);
+      for (size_t q = 0; q < acc.size(); ++q)
+        HC(ctx, hipMemcpyAsync(col(lock_off + nacc - (int)acc.size() + (int)q),
+                               Uc + (int64_t)acc[q] * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st()));
+    }
+    nlock = nacc;
   }
 
   // Rayleigh-Ritz on T_dim, locking and thick restart.
@@ -901,7 +977,7 @@ struct Slice {
     for (int j = 0; j < k; ++j) {
       out->lam[j] = lam[idx[j]];
       out->res[j] = res[idx[j]];
-      HC(ctx, hipMemcpyAsync(out->Y + (int64_t)j * n, col(idx[j]), sizeof(double) * n,
+      HC(ctx, hipMemcpyAsync(out->Y + (int64_t)j * n, col(lock_off + idx[j]), sizeof(double) * n,
                              hipMemcpyDeviceToDevice, st()));
     }
     HC(ctx, hipStreamSynchronize(st()));

@@ -117,7 +117,7 @@ def _ld(n: int) -> int:
 
 def _blk_partials(n: int, nc: int) -> int:
     r0 = _TPB // nc if nc <= _TPB else 1
-    passes = max(1, min(4 if nc <= _TPB else 8, _TPB // r0))
+    passes = max(1, min(4 if (nc <= _TPB and r0 > 2) else 8, _TPB // r0))
     rpw = r0 * passes
     gy = 1 if nc <= _TPB else (nc + _TPB - 1) // _TPB
     return (n + rpw - 1) // rpw * gy

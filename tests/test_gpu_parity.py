@@ -110,6 +110,33 @@ def test_filter_wide_block_matches_oracle(ctx, ncols, blk_variant):
     ev.evsl_set_block_variant(2)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_filter_block_beyond_32bit_offsets(ctx, prec):
+    """n * ld >= 2^31 elements: the LDS kernel with 64-bit offsets, checked on
+    sampled columns (first, middle, last) against the oracle at full size."""
+    N, ncols = 2900, 256
+    A = I.laplacian(N, 2, pot_seed=4)
+    assert A.n * ncols >= 2 ** 31
+    Ad = ev.DeviceCsr.from_host(A)
+    p8 = ev.evsl_cheb_coeffs([2.0, 2.0001, 0.0, 9.0], max_deg=8)
+    assert p8.deg == 8
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    V = torch.randn((A.n, ncols), dtype=torch.float64, device="cuda", generator=g).to(dt)
+    Y = torch.empty_like(V)
+    Am = Ad if prec == "f64" else Ad.with_values(Ad.val.float())
+    ev.evsl_filter_apply(ctx, Am, [p8], [0] * ncols, V, Y)
+    torch.cuda.synchronize()
+    for c in (0, ncols // 2 + 1, ncols - 1):
+        v = V[:, c].double().cpu().numpy()
+        ref = oracle.filter_apply(A, p8.cc, p8.dd, p8.coef, v)
+        err = np.linalg.norm(Y[:, c].double().cpu().numpy() - ref) / np.linalg.norm(v)
+        assert err <= (1e-13 if prec == "f64" else 8 * 6e-8 * 8), (c, err)
+    del V, Y
+    torch.cuda.empty_cache()
+
+
 def test_filter_dense_rows_fall_back(ctx):
     """A matrix whose rows exceed the LDS stage (a dense 300 x 300 block)."""
     rng = np.random.default_rng(2)

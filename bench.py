@@ -59,6 +59,12 @@ def parse():
                     help="filter SpMM only: FP64 and FP32 on an n x columns block")
     ap.add_argument("--columns", type=int, default=512)
     ap.add_argument("--degrees", type=int, nargs="+", default=[50, 100, 200, 300])
+    ap.add_argument("--paper-table", action="store_true",
+                    help="the twelve Laplacian problems of the paper's Section 4.1 tables, "
+                         "solved by the non-restart filtered Lanczos")
+    ap.add_argument("--rows", type=int, nargs="+", default=None,
+                    help="--paper-table: rows to run (0-11, default all)")
+    ap.add_argument("--methods", nargs="+", default=["nr"], choices=["nr", "tr"])
     ap.add_argument("--serve", action="store_true",
                     help="serving workload: a Poisson stream of DOS and eigenpair requests")
     ap.add_argument("--requests", type=int, default=48)
@@ -274,6 +280,87 @@ def filter_only_main(args):
     }), flush=True)
 
 
+# The Laplacian problems of Table tab:lap (grid, printed bounds [a, b],
+# interval, count nu) with the ChebLanNr results the paper prints in Table
+# tab:lap_pol_results (deg, niter, nmv, t-mv, t-orth, t-tot in seconds on the
+# paper's CPU), quoted as context.
+PAPER_ROWS = [
+    # dim, N, [a, b], [xi, eta], nu, deg, niter, nmv, t_mv, t_orth, t_tot
+    (2, 343, (0, 7.9998), (0.40, 0.436), 356, 157, 1290, 203200, 10.66, 24.11, 51.95),
+    (2, 343, (0, 7.9998), (1.00, 1.033), 347, 256, 1310, 336219, 17.39, 25.48, 66.71),
+    (2, 729, (0, 7.9998), (0.40, 0.410), 446, 557, 1610, 898330, 182.51, 168.20, 497.78),
+    (2, 729, (0, 7.9998), (1.00, 1.009), 435, 936, 1590, 1490547, 294.33, 179.45, 679.08),
+    (2, 1000, (0, 7.9998), (0.40, 0.405), 429, 1111, 1530, 1702481, 1451.40, 308.98, 2410.99),
+    (2, 1000, (0, 7.9998), (1.00, 1.005), 460, 1684, 1670, 2816108, 2402.99, 367.49, 3804.91),
+    (3, 49, (0, 11.9882), (0.40, 0.570), 343, 43, 1290, 55899, 3.81, 26.53, 41.03),
+    (3, 49, (0, 11.9882), (1.00, 1.100), 345, 107, 1270, 136449, 9.80, 24.25, 47.00),
+    (3, 81, (0, 11.9882), (0.40, 0.450), 433, 141, 1590, 224905, 77.24, 189.91, 359.61),
+    (3, 81, (0, 11.9882), (1.00, 1.028), 420, 378, 1570, 594636, 191.42, 168.33, 494.66),
+    (3, 100, (0, 11.9882), (0.40, 0.428), 454, 248, 1710, 425030, 563.36, 398.70, 1250.26),
+    (3, 100, (0, 11.9882), (1.00, 1.018), 475, 588, 1830, 1077689, 1357.12, 426.17, 2314.43),
+]
+
+
+def paper_table_main(args):
+    """The paper's Laplacian experiments on one GPU: for each problem, the
+    filter (sigma damping, tau = 0.8, from the printed bounds) and the filtered
+    Lanczos solve at tol 1e-8; the eigenvalues are checked against the closed
+    form 4 - 2 cos(i pi/(N+1)) - 2 cos(j pi/(N+1)) (and the 3-D analogue)."""
+    import torch
+
+    import evsl_inputs as I
+    import paper_1802_05215_amd as ev
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    ctx = ev.Ctx()
+    rows = args.rows if args.rows is not None else range(len(PAPER_ROWS))
+    out = []
+    for ri in rows:
+        dim, N, ab, iv, nu, pdeg, pniter, pnmv, ptmv, ptorth, pttot = PAPER_ROWS[ri]
+        A = I.laplacian(N, dim)
+        Ad = ev.DeviceCsr.from_host(A, device="cuda:0")
+        c = 2.0 - 2.0 * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+        ex = (c[:, None] + c[None, :]) if dim == 2 else \
+            (c[:, None, None] + c[None, :, None] + c[None, None, :])
+        ex = np.sort(ex.ravel())
+        want = ex[(ex >= iv[0]) & (ex <= iv[1])]
+        intv = [iv[0], iv[1], ab[0], ab[1]]
+        pol = ev.evsl_cheb_coeffs(intv, damping=ev.DAMP_SIGMA, tau=0.8, tau_ext=0.4)
+        for meth in args.methods:
+            mcode = ev.EVSL_LAN_NR if meth == "nr" else ev.EVSL_LAN_TR
+            opts = ev.lan_opts(tol=args.tol, seed=2, nev_est=len(want), method=mcode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, intv, pol, opts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            del Y
+            err = float(np.abs(lam - want).max()) if len(lam) == len(want) else None
+            rec = {"grid": f"{N}^{dim}", "interval": list(iv), "method": meth,
+                   "nu_closed_form": int(len(want)), "nu_paper": nu, "found": int(len(lam)),
+                   "max_abs_err": err, "max_res": float(res.max()) if len(res) else None,
+                   "deg": pol.deg, "deg_paper": pdeg, "niter": st["niter"], "niter_paper": pniter,
+                   "nmv": st["nmv"], "nmv_paper": pnmv, "t_mv": st["t_mv"],
+                   "t_orth": st["t_orth"], "t_ritz": st["t_ritz"], "t_tot": dt,
+                   "t_tot_paper_cpu": pttot, "eig_per_s": len(lam) / dt, "status": st["status"]}
+            out.append(rec)
+            log(f"[paper] {rec['grid']} {iv} {meth}: found {rec['found']}/{len(want)} "
+                f"deg {pol.deg} (paper {pdeg}) niter {st['niter']} (paper {pniter}) "
+                f"t {dt:.2f} s (paper {pttot} s CPU) err {err}")
+        del Ad
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "eigenpairs/s on the paper's Laplacian problems (non-restart filtered Lanczos)",
+        "unit": "eigenpairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Table tab:lap problems: 2-D 5-point / 3-D 7-point Laplacians, "
+                               "printed [a, b], sigma damping, tau 0.8, "
+                               f"tol {args.tol:g}"},
+        "rows": out}), flush=True)
+
+
 def serve_main(args):
     """Serving workload: a seeded Poisson stream of requests, each on its own
     matrix, admitted by device-memory footprint and run concurrently (one HIP
@@ -362,7 +449,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.serve or args.filter_only:
+    if args.serve or args.filter_only or args.paper_table:
         import torch
         import paper_1802_05215_amd as ev
         if not torch.cuda.is_available():
@@ -372,6 +459,8 @@ def main():
         torch.cuda.set_device(0)
         if args.serve:
             serve_main(args)
+        elif args.paper_table:
+            paper_table_main(args)
         else:
             filter_only_main(args)
         return

@@ -52,6 +52,11 @@ class LanOpts(C.Structure):
                 ("seed", C.c_uint64), ("nev_cap", C.c_int)]
 
 
+class SiOpts(C.Structure):
+    _fields_ = [("block", C.c_int), ("max_its", C.c_int), ("tol", C.c_double),
+                ("seed", C.c_uint64), ("nev_cap", C.c_int)]
+
+
 class LanStats(C.Structure):
     _fields_ = [("nev", C.c_int), ("niter", C.c_int), ("nmv", C.c_int), ("nrestart", C.c_int),
                 ("status", C.c_int)]
@@ -83,6 +88,8 @@ def _setup(L):
     L.or_filtered_lanczos.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
                                       C.POINTER(LanOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
     L.or_filtered_lanczos_nr.argtypes = L.or_filtered_lanczos.argtypes
+    L.or_filtered_subspace.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
+                                       C.POINTER(SiOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
 
 
 def _d(a):
@@ -267,4 +274,35 @@ def filtered_lanczos_nr(A, intv, pol, m=None, ncycle=30, tol=1e-10, seed=2, nev_
         raise ValueError("filtered_lanczos_nr: invalid arguments")
     k = st.nev
     stats = dict(nev=k, niter=st.niter, nmv=st.nmv, nrestart=st.nrestart, status=st.status)
+    return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats
+
+
+def filtered_subspace(A, intv, pol, block=None, max_its=200, tol=1e-10, seed=2, nev_cap=None,
+                      nev_est=None):
+    """Filtered subspace iteration on one slice with a block of `block`
+    vectors (default 3 nev_est + 8). Returns (lam, Y (n x nev), res, stats)."""
+    if nev_est is None:
+        nev_est = 50
+    if block is None:
+        block = 3 * int(nev_est) + 8
+    block = min(block, A.n)
+    if nev_cap is None:
+        nev_cap = block
+    n = A.n
+    iv = _f64(intv)
+    coef = _f64(pol["coef"])
+    lam = np.empty(nev_cap)
+    res = np.empty(nev_cap)
+    Y = np.empty((nev_cap, n))
+    opts = SiOpts(block, max_its, tol, seed, nev_cap)
+    st = LanStats()
+    rp, ci, va = (np.ascontiguousarray(A.row_ptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+                  _f64(A.val))
+    rc = lib().or_filtered_subspace(n, _i(rp), _i(ci), _d(va), _d(iv), len(coef) - 1, _d(coef),
+                                    pol["bar"], C.byref(opts), _d(lam), _d(res), _d(Y),
+                                    C.byref(st))
+    if rc != 0:
+        raise ValueError("filtered_subspace: invalid arguments")
+    k = st.nev
+    stats = dict(nev=k, niter=st.niter, nmv=st.nmv, status=st.status)
     return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats

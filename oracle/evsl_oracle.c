@@ -813,3 +813,125 @@ int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, cons
   free(Q); free(T); free(Tw); free(w); free(Yv); free(z); free(u); free(au); free(h);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Filtered subspace iteration. The paper names the method and notes that its
+ * block size comes from the DOS count; the stopping rule, the start block and
+ * the orthonormalisation are this reading's. */
+static int orthonormalise_block(int64_t n, int b, double *W, double *h) {
+  /* column j <- column j minus its projections on columns < j (two passes),
+   * normalised; a column that vanishes (relative norm < 1e-10) is replaced by
+   * zeros and reported */
+  int lost = 0;
+  for (int j = 0; j < b; ++j) {
+    double *w = W + (size_t)j * n;
+    double n0 = nrm2(n, w);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) h[i] = dot(n, W + (size_t)i * n, w);
+      for (int i = 0; i < j; ++i)
+        for (int64_t r = 0; r < n; ++r) w[r] -= h[i] * W[(size_t)i * n + r];
+    }
+    double nw = nrm2(n, w);
+    if (!(nw > 1e-10 * n0)) {
+      memset(w, 0, sizeof(double) * n);
+      lost++;
+      continue;
+    }
+    for (int64_t r = 0; r < n; ++r) w[r] /= nw;
+  }
+  return lost;
+}
+
+int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                         const double intv[4], int deg, const double *coef, double bar,
+                         const or_si_opts *opt, double *lam, double *res, double *Y,
+                         or_lan_stats *st) {
+  memset(st, 0, sizeof(*st));
+  const double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  const double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
+  const double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
+  const int b = opt->block;
+  if (b < 1 || b > n || deg < 1 || opt->max_its < 1) return -1;
+  double *V = (double *)malloc(sizeof(double) * (size_t)n * b);
+  double *W = (double *)malloc(sizeof(double) * (size_t)n * b);
+  double *AQ = (double *)malloc(sizeof(double) * (size_t)n * b);
+  double *H = (double *)malloc(sizeof(double) * (size_t)b * b);
+  double *S = (double *)malloc(sizeof(double) * (size_t)b * b);
+  double *th = (double *)malloc(sizeof(double) * b);
+  double *rs = (double *)malloc(sizeof(double) * b);
+  double *mu = (double *)malloc(sizeof(double) * b);
+  double *h = (double *)malloc(sizeof(double) * (b + 1));
+  double *z = (double *)malloc(sizeof(double) * n);
+  int its = 0, nmv = 0, status = 1, prev = -1, have_ritz = 0;
+  for (int j = 0; j < b; ++j) or_lanczos_start(opt->seed, n, j, V + (size_t)j * n);
+  orthonormalise_block(n, b, V, h);
+  while (its < opt->max_its) {
+    /* W = p(A-hat) V */
+    for (int j = 0; j < b; ++j)
+      or_filter_apply(n, rp, ci, va, cc, dd, deg, coef, 1, V + (size_t)j * n, W + (size_t)j * n);
+    its++;
+    nmv += deg * b;
+    if (have_ritz) {
+      int nconv = 0, bad = 0, nin = 0;
+      for (int j = 0; j < b; ++j) {
+        mu[j] = dot(n, V + (size_t)j * n, W + (size_t)j * n);
+        if (th[j] < tlo || th[j] > thi) continue;
+        nin++;
+        if (rs[j] <= opt->tol) nconv++;
+        else if (mu[j] >= bar) bad++;
+      }
+      if (nin == b) { status = 3; break; }
+      if (nconv == prev && bad == 0) { status = 0; break; }
+      prev = nconv;
+    }
+    /* orthonormal basis Q of span(W) (in W), A Q, Rayleigh-Ritz */
+    orthonormalise_block(n, b, W, h);
+    for (int j = 0; j < b; ++j) or_spmv(n, rp, ci, va, W + (size_t)j * n, AQ + (size_t)j * n);
+    nmv += b;
+    for (int j = 0; j < b; ++j)
+      for (int i = 0; i < b; ++i) H[i + (size_t)j * b] = dot(n, W + (size_t)i * n, AQ + (size_t)j * n);
+    for (int j = 0; j < b; ++j)
+      for (int i = 0; i < j; ++i) {
+        double avg = 0.5 * (H[i + (size_t)j * b] + H[j + (size_t)i * b]);
+        H[i + (size_t)j * b] = H[j + (size_t)i * b] = avg;
+      }
+    or_jacobi_eig(b, H, th, S);
+    /* V = Q S, residuals ||A v - theta v|| = ||AQ s - theta Q s|| */
+    for (int j = 0; j < b; ++j) {
+      double *v = V + (size_t)j * n;
+      for (int64_t r = 0; r < n; ++r) {
+        double sv = 0.0, sa = 0.0;
+        for (int p = 0; p < b; ++p) {
+          sv += W[(size_t)p * n + r] * S[p + (size_t)j * b];
+          sa += AQ[(size_t)p * n + r] * S[p + (size_t)j * b];
+        }
+        v[r] = sv;
+        z[r] = sa;
+      }
+      double rr = 0.0;
+      for (int64_t r = 0; r < n; ++r) {
+        double e = z[r] - th[j] * v[r];
+        rr += e * e;
+      }
+      rs[j] = sqrt(rr) / normA;
+    }
+    have_ritz = 1;
+  }
+  /* converged pairs inside the slice, ascending (the Ritz values are sorted) */
+  int nev = 0;
+  for (int j = 0; j < b; ++j) {
+    if (th[j] < tlo || th[j] > thi || rs[j] > opt->tol) continue;
+    if (nev >= opt->nev_cap) { status = 2; break; }
+    memcpy(Y + (size_t)nev * n, V + (size_t)j * n, sizeof(double) * n);
+    lam[nev] = th[j];
+    res[nev] = rs[j];
+    nev++;
+  }
+  st->nev = nev;
+  st->niter = its;
+  st->nmv = nmv;
+  st->nrestart = 0;
+  st->status = status;
+  free(V); free(W); free(AQ); free(H); free(S); free(th); free(rs); free(mu); free(h); free(z);
+  return 0;
+}

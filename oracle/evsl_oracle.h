@@ -125,6 +125,30 @@ int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, cons
                            const or_lan_opts *opt, double *lam, double *res, double *Y,
                            or_lan_stats *st);
 
+typedef struct {
+  int block;      /* subspace dimension b */
+  int max_its;    /* cap on iterations */
+  double tol;     /* residual tolerance relative to ||A|| */
+  uint64_t seed;  /* start-block stream: column j is the Lanczos start vector of block j */
+  int nev_cap;    /* capacity of lam/res/Y */
+} or_si_opts;
+
+/* Filtered subspace iteration (ChebSI, Sections 2.6 and 3): V <- p(A-hat) V,
+ * orthonormalised (classical Gram-Schmidt, two passes), then Rayleigh-Ritz
+ * with A. After each filter application mu_j = v_j^T p(A-hat) v_j is known for
+ * the current Ritz vectors; the run stops when the number of converged Ritz
+ * pairs inside the slice (residual <= tol) is the same as at the previous
+ * iteration and no unconverged Ritz value inside the slice has mu_j >= bar
+ * (such a pair would be a wanted eigenvector still converging; an unconverged
+ * pair with mu_j < bar is a mixture of eigenvectors outside the slice).
+ * Outputs as or_filtered_lanczos; st->niter counts iterations (filter
+ * applications to the block), st->status: 0 stopped by the rule, 1 max_its,
+ * 2 capacity exceeded, 3 the slice filled the subspace (b too small). */
+int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                         const double intv[4], int deg, const double *coef, double bar,
+                         const or_si_opts *opt, double *lam, double *res, double *Y,
+                         or_lan_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

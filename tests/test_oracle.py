@@ -429,6 +429,63 @@ def test_filtered_lanczos_nr_step_cap_reports_unsettled():
     assert np.all(res <= 1e-10) and np.all((lam >= 1.0) & (lam <= 1.5))
 
 
+# ---------------------------------------------------------------- subspace iteration
+def test_filtered_subspace_32x32_all_with_multiplicity():
+    A = I.laplacian(32, 2)
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    intv = [1.0, 1.5, lo, hi]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_JACKSON)
+    ex = lap_eigs(32, 2)
+    want = ex[(ex >= 1.0) & (ex <= 1.5)]
+    assert len(np.unique(np.round(want, 10))) < len(want)
+    lam, Y, res, st = oracle.filtered_subspace(A, intv, p, tol=1e-10, nev_est=len(want))
+    assert st["nev"] == len(want) and st["status"] == 0
+    assert np.abs(lam - want).max() <= 1e-12 * np.abs(want).max()
+    assert res.max() <= 1e-10
+    assert np.abs(Y.T @ Y - np.eye(len(want))).max() <= 1e-10
+    b = 3 * len(want) + 8
+    assert st["nmv"] == st["niter"] * b * p["deg"] + (st["niter"] - 1) * b
+
+
+def test_filtered_subspace_with_potential_matches_dense_and_lanczos():
+    A = I.laplacian(20, 2, pot_seed=0)
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    intv = [2.0, 2.6, lo, hi]
+    want = w[(w >= 2.0) & (w <= 2.6)]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_JACKSON)
+    lam, Y, res, st = oracle.filtered_subspace(A, intv, p, tol=1e-10, nev_est=len(want))
+    assert len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-10 * np.abs(want).max()
+    R = A.to_dense() @ Y - Y * lam
+    assert np.linalg.norm(R, axis=0).max() <= 1e-10 * max(abs(lo), abs(hi))
+    lam2, _, _, _ = oracle.filtered_lanczos(A, intv, p, tol=1e-10, nev_est=len(want))
+    assert np.abs(lam - lam2).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_filtered_subspace_boundary_empty_and_small_block():
+    A = I.laplacian(10, 3)
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    ex = lap_eigs(10, 3)
+    intv = [lo, 1.4, lo, hi]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_SIGMA, tau_ext=0.4)
+    want = ex[ex <= 1.4]
+    lam, Y, res, st = oracle.filtered_subspace(A, intv, p, tol=1e-10, nev_est=len(want))
+    assert len(lam) == len(want) and st["status"] == 0
+    assert np.abs(lam - want).max() <= 1e-12 * 12
+    # a block smaller than the count: every Ritz value lands in the slice
+    lam, Y, res, st = oracle.filtered_subspace(A, intv, p, block=len(want) - 5, tol=1e-10)
+    assert st["status"] == 3
+    B = I.laplacian(12, 2)
+    u = np.unique(np.round(lap_eigs(12, 2), 12))
+    i = np.argmax(np.diff(u[10:50])) + 10
+    a, b = u[i] + 0.2 * (u[i + 1] - u[i]), u[i + 1] - 0.2 * (u[i + 1] - u[i])
+    lo, hi = oracle.lanczos_bounds(B, 80, 3)
+    p = oracle.find_pol([a, b, lo, hi], damping=oracle.DAMP_SIGMA)
+    lam, Y, res, st = oracle.filtered_subspace(B, [a, b, lo, hi], p, tol=1e-10, nev_est=3)
+    assert len(lam) == 0 and st["status"] == 0
+
+
 def test_paper_counts_from_closed_form():
     for r in GOLD["lap_problems"]["rows"]:
         if r["n"] > 600000:

@@ -46,7 +46,7 @@ extern "C" {
 
 /* ---- Lanczos variant of a slice (evsl_lan_opts_t.method) ---- */
 #define EVSL_LAN_TR 0 /* thick restart with locking (ChebLanTr, Algorithm alg:FiltLanTR) */
-#define EVSL_LAN_NR 1 /* non-restart (ChebLanNr, Sections 2.4 and 3) */
+#define EVSL_LAN_NR 1 /* non-restart (ChebLanNr, Sections 2.3 and 3.1) */
 
 /* ---- damping of the Chebyshev expansion ---- */
 #define EVSL_DAMP_NONE 0
@@ -214,6 +214,36 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
 int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices,
                                 const double *intv, const evsl_pol_t *pols,
                                 const evsl_lan_opts_t *opts, evsl_eigs_t *outs);
+
+/* ---- 6. filtered subspace iteration (ChebSI; end of Section 2.5 and Section
+ * 3.1: a projection method beside Lanczos whose block size comes from the DOS
+ * count) on one or several slices ----
+ * Each iteration filters the slice's block V (n x block) with p(A-hat),
+ * orthonormalises the result (two SVQB passes: Gram matrix on FP64 MFMA,
+ * eigen-decomposition on the host; directions lost to rank deficiency are
+ * replaced by further random vectors of the seed's stream) and runs
+ * Rayleigh-Ritz with A. The run ends when the count of converged Ritz pairs in
+ * the slice (residual <= tol) repeats and no unconverged Ritz value in the
+ * slice has a filter Rayleigh quotient v^T p(A-hat) v >= bar. Returns the
+ * converged pairs in the slice. EVSL_ENOCONV (with the pairs found) when
+ * max_its is reached or when every Ritz value lies in the slice (block too
+ * small for the slice's count). Device memory per slice: 3 n x block FP64
+ * plus, for the batch, 3 n x (sum of blocks) for the filter. In a batch all
+ * active slices' blocks are filtered together, one block SpMM launch per
+ * degree step. Synchronous. out->nrestart counts replaced directions. */
+typedef struct {
+  int block;      /* subspace dimension; 0: 3 nev_est + 8 (at most n) */
+  int max_its;    /* cap on iterations (filter applications); 0: 100 */
+  double tol;     /* residual tolerance ||A u - lambda u|| / ||A||; 0: 1e-8 */
+  uint64_t seed;  /* start block: column j is restart block j of the Lanczos start stream */
+  int nev_est;    /* expected count in the slice (sizes the block); 0: 50 */
+  int reserved[3];
+} evsl_si_opts_t;
+int evsl_filtered_subspace(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4],
+                           const evsl_pol_t *pol, const evsl_si_opts_t *opt, evsl_eigs_t *out);
+int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices,
+                                 const double *intv, const evsl_pol_t *pols,
+                                 const evsl_si_opts_t *opts, evsl_eigs_t *outs);
 
 /* Copies the result vectors into a caller-owned device array dst (column j
  * of out->Y to dst + j*ldd, ldd >= n). Asynchronous on the context stream. */

@@ -818,28 +818,32 @@ int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, cons
 /* Filtered subspace iteration. The paper names the method and notes that its
  * block size comes from the DOS count; the stopping rule, the start block and
  * the orthonormalisation are this reading's. */
-static int orthonormalise_block(int64_t n, int b, double *W, double *h) {
+static int orthonormalise_block(int64_t n, int b, double *W, double *h, uint64_t seed,
+                                int *next) {
   /* column j <- column j minus its projections on columns < j (two passes),
    * normalised; a column that vanishes (relative norm < 1e-10) is replaced by
-   * zeros and reported */
-  int lost = 0;
+   * the next random vector of the stream and orthogonalised again; returns
+   * the number of replacements */
+  int refills = 0;
   for (int j = 0; j < b; ++j) {
     double *w = W + (size_t)j * n;
-    double n0 = nrm2(n, w);
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i < j; ++i) h[i] = dot(n, W + (size_t)i * n, w);
-      for (int i = 0; i < j; ++i)
-        for (int64_t r = 0; r < n; ++r) w[r] -= h[i] * W[(size_t)i * n + r];
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      double n0 = nrm2(n, w);
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < j; ++i) h[i] = dot(n, W + (size_t)i * n, w);
+        for (int i = 0; i < j; ++i)
+          for (int64_t r = 0; r < n; ++r) w[r] -= h[i] * W[(size_t)i * n + r];
+      }
+      double nw = nrm2(n, w);
+      if (nw > 1e-10 * n0) {
+        for (int64_t r = 0; r < n; ++r) w[r] /= nw;
+        break;
+      }
+      or_lanczos_start(seed, n, (*next)++, w);
+      refills++;
     }
-    double nw = nrm2(n, w);
-    if (!(nw > 1e-10 * n0)) {
-      memset(w, 0, sizeof(double) * n);
-      lost++;
-      continue;
-    }
-    for (int64_t r = 0; r < n; ++r) w[r] /= nw;
   }
-  return lost;
+  return refills;
 }
 
 int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
@@ -863,8 +867,9 @@ int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const 
   double *h = (double *)malloc(sizeof(double) * (b + 1));
   double *z = (double *)malloc(sizeof(double) * n);
   int its = 0, nmv = 0, status = 1, prev = -1, have_ritz = 0;
+  int next = b;  /* next random block of the stream (refills) */
   for (int j = 0; j < b; ++j) or_lanczos_start(opt->seed, n, j, V + (size_t)j * n);
-  orthonormalise_block(n, b, V, h);
+  orthonormalise_block(n, b, V, h, opt->seed, &next);
   while (its < opt->max_its) {
     /* W = p(A-hat) V */
     for (int j = 0; j < b; ++j)
@@ -885,7 +890,7 @@ int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const 
       prev = nconv;
     }
     /* orthonormal basis Q of span(W) (in W), A Q, Rayleigh-Ritz */
-    orthonormalise_block(n, b, W, h);
+    orthonormalise_block(n, b, W, h, opt->seed, &next);
     for (int j = 0; j < b; ++j) or_spmv(n, rp, ci, va, W + (size_t)j * n, AQ + (size_t)j * n);
     nmv += b;
     for (int j = 0; j < b; ++j)

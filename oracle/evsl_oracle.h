@@ -112,7 +112,7 @@ int or_filtered_lanczos(int64_t n, const int32_t *rp, const int32_t *ci, const d
                         const or_lan_opts *opt, double *lam, double *res, double *Y,
                         or_lan_stats *st);
 
-/* Filtered non-restart Lanczos (ChebLanNr, Section 2.4 and the solver list of
+/* Filtered non-restart Lanczos (ChebLanNr, Section 2.3 and the solver list of
  * Section 3): Lanczos on p(A-hat) from one seeded random vector, with full
  * reorthogonalisation, up to opt->m steps; every opt->ncycle steps the sum of
  * the Ritz values >= bar is compared with its value at the previous test, and
@@ -133,8 +133,9 @@ typedef struct {
   int nev_cap;    /* capacity of lam/res/Y */
 } or_si_opts;
 
-/* Filtered subspace iteration (ChebSI, Sections 2.6 and 3): V <- p(A-hat) V,
- * orthonormalised (classical Gram-Schmidt, two passes), then Rayleigh-Ritz
+/* Filtered subspace iteration (ChebSI, end of Section 2.5 and Section 3.1): V <- p(A-hat) V,
+ * orthonormalised (classical Gram-Schmidt, two passes; a column that vanishes
+ * is replaced by the next random vector of the stream), then Rayleigh-Ritz
  * with A. After each filter application mu_j = v_j^T p(A-hat) v_j is known for
  * the current Ritz vectors; the run stops when the number of converged Ritz
  * pairs inside the slice (residual <= tol) is the same as at the previous

@@ -30,7 +30,7 @@ EXPORTS = [
     "evsl_filtered_lanczos_batch", "evsl_eigs_get_vectors", "evsl_eigs_free",
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
     "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
-    "evsl_gram", "evsl_mem_stats",
+    "evsl_gram", "evsl_mem_stats", "evsl_filtered_subspace", "evsl_filtered_subspace_batch",
 ]
 
 
@@ -58,6 +58,11 @@ class LanOptsT(C.Structure):
                 ("prec", C.c_int), ("val32", C.c_void_p), ("tol_lo", C.c_double),
                 ("polish", C.c_int), ("polish_div", C.c_int), ("method", C.c_int),
                 ("reserved", C.c_int)]
+
+
+class SiOptsT(C.Structure):
+    _fields_ = [("block", C.c_int), ("max_its", C.c_int), ("tol", C.c_double),
+                ("seed", C.c_uint64), ("nev_est", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class EigsT(C.Structure):
@@ -111,6 +116,11 @@ def _lib():
                                     C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
         L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
+        L.evsl_filtered_subspace.argtypes = [C.c_void_p, C.POINTER(CsrT), _dp, C.POINTER(PolT),
+                                             C.POINTER(SiOptsT), C.POINTER(EigsT)]
+        L.evsl_filtered_subspace_batch.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, _dp,
+                                                   C.POINTER(PolT), C.POINTER(SiOptsT),
+                                                   C.POINTER(EigsT)]
         L.evsl_mem_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                      C.c_int]
         L.evsl_gram.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p, C.c_int64,
@@ -364,4 +374,30 @@ def evsl_filtered_lanczos_batch(ctx, A, intvs, pols, opts_list):
     outs = (EigsT * ns)()
     _chk(_lib().evsl_filtered_lanczos_batch(ctx.h, C.byref(A.t), ns, _dptr(iv), parr, oarr, outs),
          "evsl_filtered_lanczos_batch", ok=(EVSL_OK, EVSL_ENOCONV))
+    return [_take(ctx, outs[q], A.n, A.val.device) for q in range(ns)]
+
+
+def si_opts(block=0, max_its=0, tol=1e-8, seed=2, nev_est=0):
+    return SiOptsT(block, max_its, tol, seed, nev_est, (C.c_int * 3)())
+
+
+def evsl_filtered_subspace(ctx, A, intv, pol, opts=None):
+    """Filtered subspace iteration on one slice: (lam, Y, res, stats)."""
+    iv = _f64(intv)
+    out = EigsT()
+    opts = opts or si_opts()
+    _chk(_lib().evsl_filtered_subspace(ctx.h, C.byref(A.t), _dptr(iv), C.byref(pol.t),
+                                       C.byref(opts), C.byref(out)), "evsl_filtered_subspace",
+         ok=(EVSL_OK, EVSL_ENOCONV))
+    return _take(ctx, out, A.n, A.val.device)
+
+
+def evsl_filtered_subspace_batch(ctx, A, intvs, pols, opts_list):
+    ns = len(pols)
+    iv = _f64(np.asarray(intvs).reshape(-1))
+    parr = (PolT * ns)(*[p.t for p in pols])
+    oarr = (SiOptsT * ns)(*opts_list)
+    outs = (EigsT * ns)()
+    _chk(_lib().evsl_filtered_subspace_batch(ctx.h, C.byref(A.t), ns, _dptr(iv), parr, oarr, outs),
+         "evsl_filtered_subspace_batch", ok=(EVSL_OK, EVSL_ENOCONV))
     return [_take(ctx, outs[q], A.n, A.val.device) for q in range(ns)]

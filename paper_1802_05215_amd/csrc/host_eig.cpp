@@ -14,6 +14,11 @@ namespace evh {
 
 int sym_eig(int m, double *A, double *w, double *V) {
   if (m <= 0) return -1;
+  if (m == 1) {
+    w[0] = A[0];
+    if (V) V[0] = 1.0;
+    return 0;
+  }
   auto a = [&](int i, int j) -> double & { return A[i + (size_t)j * m]; };
   if (V) {
     std::fill(V, V + (size_t)m * m, 0.0);
@@ -64,7 +69,13 @@ int sym_eig(int m, double *A, double *w, double *V) {
   std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
   for (int i = 0; i < m; ++i) d[i] = a(i, i);
   for (int i = 0; i + 1 < m; ++i) e[i] = a(i + 1, i);
-  // --- implicit QR on the tridiagonal (d, e)
+  return tridiag_eig(m, d.data(), e.data(), w, V);
+}
+
+// Implicit symmetric QR on the tridiagonal (d, e); V (m x m) accumulates the
+// rotations when not null (it must hold the transformation so far).
+int tridiag_eig(int m, double *d, double *e, double *w, double *V) {
+  if (m <= 0) return -1;
   const double eps = 2.220446049250313e-16;
   int hi = m - 1;
   for (long iter = 0; hi > 0 && iter < 60L * m + 100; ++iter) {
@@ -154,6 +165,103 @@ void tri_inv_upper(int m, const double *R, double *Ri) {
       for (int k = i + 1; k <= j; ++k) s += R[i + (size_t)k * m] * Ri[k + (size_t)j * m];
       Ri[i + (size_t)j * m] = -s / R[i + (size_t)i * m];
     }
+  }
+}
+
+// Eigenvectors of the symmetric tridiagonal (d, e) for the eigenvalues lam
+// (ascending, nsel of them) by inverse iteration: T - x I is factored by
+// Gaussian elimination with partial pivoting (U has two superdiagonals), three
+// solves from a fixed start vector, each result orthogonalised (modified
+// Gram-Schmidt) against the vectors already computed for eigenvalues of the
+// same cluster (gaps below 1e-3 ||T||), whose shifts are pushed apart by
+// 10 eps |x| so that the factorisations differ. Z is m x nsel column-major.
+void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const double *lam,
+                     double *Z) {
+  const double eps = 2.220446049250313e-16;
+  double tnorm = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double r = std::fabs(d[i]);
+    if (i > 0) r += std::fabs(e[i - 1]);
+    if (i + 1 < m) r += std::fabs(e[i]);
+    tnorm = std::max(tnorm, r);
+  }
+  const double tiny = std::max(eps * tnorm, 1e-300);
+  const double clus = 1e-3 * tnorm;
+  std::vector<double> a(m), up(m), up2(m), lo(m), y(m);
+  std::vector<char> swp(m);
+  int cstart = 0;
+  double xprev = 0.0;
+  for (int j = 0; j < nsel; ++j) {
+    double x = lam[j];
+    if (j > 0 && lam[j] - lam[j - 1] < clus) {
+      const double push = 10.0 * eps * std::fabs(x) + tiny;
+      if (x - xprev < push) x = xprev + push;
+    } else {
+      cstart = j;
+    }
+    xprev = x;
+    // factor T - x I
+    for (int i = 0; i < m; ++i) {
+      a[i] = d[i] - x;
+      up[i] = i + 1 < m ? e[i] : 0.0;
+      up2[i] = 0.0;
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+      const double sub = e[i];
+      if (std::fabs(a[i]) >= std::fabs(sub)) {
+        if (a[i] == 0.0) a[i] = tiny;
+        lo[i] = sub / a[i];
+        swp[i] = 0;
+        a[i + 1] -= lo[i] * up[i];
+      } else {
+        // rows i and i+1 exchange
+        const double f = a[i] / sub;
+        lo[i] = f;
+        swp[i] = 1;
+        a[i] = sub;
+        const double t = a[i + 1];
+        a[i + 1] = up[i] - f * t;
+        if (i + 2 < m) {
+          up2[i] = up[i + 1];
+          up[i + 1] = -f * up[i + 1];
+        }
+        up[i] = t;
+      }
+    }
+    if (a[m - 1] == 0.0) a[m - 1] = tiny;
+    for (int i = 0; i < m; ++i)
+      if (std::fabs(a[i]) < tiny) a[i] = a[i] < 0 ? -tiny : tiny;
+    // start vector: a fixed, non-degenerate pattern
+    for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3 * j);
+    double *z = Z + (size_t)j * m;
+    for (int it = 0; it < 3; ++it) {
+      // forward: L with the row exchanges
+      for (int i = 0; i + 1 < m; ++i) {
+        if (swp[i]) std::swap(y[i], y[i + 1]);
+        y[i + 1] -= lo[i] * y[i];
+      }
+      // back: U with two superdiagonals
+      y[m - 1] /= a[m - 1];
+      if (m > 1) y[m - 2] = (y[m - 2] - up[m - 2] * y[m - 1]) / a[m - 2];
+      for (int i = m - 3; i >= 0; --i)
+        y[i] = (y[i] - up[i] * y[i + 1] - up2[i] * y[i + 2]) / a[i];
+      // orthogonalise against the cluster's earlier vectors, then normalise
+      for (int k = cstart; k < j; ++k) {
+        const double *zk = Z + (size_t)k * m;
+        double h = 0.0;
+        for (int i = 0; i < m; ++i) h += zk[i] * y[i];
+        for (int i = 0; i < m; ++i) y[i] -= h * zk[i];
+      }
+      double nrm = 0.0;
+      for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0)) {
+        for (int i = 0; i < m; ++i) y[i] = (i == j % m) ? 1.0 : 0.0;
+        nrm = 1.0;
+      }
+      for (int i = 0; i < m; ++i) y[i] /= nrm;
+    }
+    std::copy(y.begin(), y.end(), z);
   }
 }
 

@@ -26,6 +26,14 @@ int slice(int K, const double *mom, int damp, const double intv[4], int nslices,
 // shifts (Golub and Van Loan, Sections 8.3.1-8.3.3). w ascending; V (m x m,
 // column-major, may be null for eigenvalues only).
 int sym_eig(int m, double *A, double *w, double *V);
+// The QR phase alone, for a matrix that is already tridiagonal: diagonal d,
+// off-diagonal e (both overwritten); V as in sym_eig (identity or a prior
+// transformation, m x m) or null. O(m^2) without vectors.
+int tridiag_eig(int m, double *d, double *e, double *w, double *V);
+// Eigenvectors of the tridiagonal (d, e) for nsel eigenvalues lam (ascending)
+// by inverse iteration; Z is m x nsel column-major.
+void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const double *lam,
+                     double *Z);
 // Cholesky G = R^T R (R upper triangular); -1 if G is not positive definite.
 int chol_upper(int m, const double *G, double *R);
 // Inverse of an upper-triangular matrix.

@@ -17,198 +17,12 @@
 
 #include "../../include/evsl_mi355.h"
 #include "host_poly.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 
-namespace {
-
-struct Error {
-  int code;
-};
-
-[[noreturn]] void fail(int code) { throw Error{code}; }
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-}  // namespace
-
-struct evsl_ctx_s {
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int last_hip = 0;
-  int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged, 3/4 unrolled
-  int group_width = 0;   // columns per block filter launch in batches (0: all)
-  bool timing = true;
-  // filter measurement
-  int64_t filt_launches = 0;
-  double filt_seconds = 0.0;
-  double filt_bytes = 0.0;
-  struct Pending {
-    hipEvent_t a, b;
-    int64_t launches;
-    double bytes;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> event_pool;
-  // grow-only workspace slots
-  std::vector<void *> ws_ptr;
-  std::vector<size_t> ws_size;
-  double *pinned = nullptr;
-  size_t pinned_cap = 0;
-  // device memory held by this context (workspace, slice buffers, results)
-  std::unordered_map<void *, size_t> live;
-  int64_t mem_cur = 0, mem_peak = 0;
-};
+using namespace evc;
 
 namespace {
-
-void hipchk(evsl_ctx_t ctx, hipError_t e) {
-  if (e != hipSuccess) {
-    if (ctx) ctx->last_hip = (int)e;
-    if (e == hipErrorOutOfMemory) fail(EVSL_ENOMEM);
-    fail(EVSL_EHIP);
-  }
-}
-#define HC(ctx, x) hipchk((ctx), (x))
-
-void *dalloc(evsl_ctx_t ctx, size_t bytes) {
-  void *p = nullptr;
-  if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->last_hip = (int)e;
-    fail(EVSL_ENOMEM);
-  }
-  ctx->live[p] = bytes;
-  ctx->mem_cur += (int64_t)bytes;
-  ctx->mem_peak = std::max(ctx->mem_peak, ctx->mem_cur);
-  return p;
-}
-
-// Frees a buffer from dalloc and takes it off the context's ledger.
-void dfree(evsl_ctx_t ctx, void *p) {
-  if (!p) return;
-  (void)hipFree(p);
-  if (!ctx) return;
-  auto it = ctx->live.find(p);
-  if (it != ctx->live.end()) {
-    ctx->mem_cur -= (int64_t)it->second;
-    ctx->live.erase(it);
-  }
-}
-
-// Workspace slot `slot` of at least `bytes` bytes (contents not preserved on growth).
-void *ws(evsl_ctx_t ctx, int slot, size_t bytes) {
-  if ((int)ctx->ws_ptr.size() <= slot) {
-    ctx->ws_ptr.resize(slot + 1, nullptr);
-    ctx->ws_size.resize(slot + 1, 0);
-  }
-  if (ctx->ws_size[slot] < bytes) {
-    if (ctx->ws_ptr[slot]) {
-      HC(ctx, hipStreamSynchronize(ctx->stream));
-      dfree(ctx, ctx->ws_ptr[slot]);
-    }
-    ctx->ws_ptr[slot] = nullptr;
-    ctx->ws_size[slot] = 0;
-    ctx->ws_ptr[slot] = dalloc(ctx, bytes);
-    ctx->ws_size[slot] = bytes;
-  }
-  return ctx->ws_ptr[slot];
-}
-
-double *pinned(evsl_ctx_t ctx, size_t count) {
-  if (ctx->pinned_cap < count) {
-    if (ctx->pinned) {
-      HC(ctx, hipStreamSynchronize(ctx->stream));
-      (void)hipHostFree(ctx->pinned);
-      ctx->pinned = nullptr;
-      ctx->pinned_cap = 0;
-    }
-    void *p = nullptr;
-    HC(ctx, hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault));
-    ctx->pinned = (double *)p;
-    ctx->pinned_cap = count;
-  }
-  return ctx->pinned;
-}
-
-hipEvent_t get_event(evsl_ctx_t ctx) {
-  if (!ctx->event_pool.empty()) {
-    hipEvent_t e = ctx->event_pool.back();
-    ctx->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e;
-  HC(ctx, hipEventCreate(&e));
-  return e;
-}
-
-// Resolve pending filter timings (waits for their completion).
-void resolve_pending(evsl_ctx_t ctx) {
-  for (auto &p : ctx->pending) {
-    HC(ctx, hipEventSynchronize(p.b));
-    float ms = 0.f;
-    HC(ctx, hipEventElapsedTime(&ms, p.a, p.b));
-    ctx->filt_seconds += ms * 1e-3;
-    ctx->filt_launches += p.launches;
-    ctx->filt_bytes += p.bytes;
-    ctx->event_pool.push_back(p.a);
-    ctx->event_pool.push_back(p.b);
-  }
-  ctx->pending.clear();
-}
-
-// Bracket a batch of filter launches with events (when timing is on).
-struct FilterTimer {
-  evsl_ctx_t ctx;
-  hipEvent_t a = nullptr, b = nullptr;
-  explicit FilterTimer(evsl_ctx_t c) : ctx(c) {
-    if (ctx->timing) {
-      a = get_event(ctx);
-      HC(ctx, hipEventRecord(a, ctx->stream));
-    }
-  }
-  void stop(int64_t launches, double bytes) {
-    if (ctx->timing) {
-      b = get_event(ctx);
-      HC(ctx, hipEventRecord(b, ctx->stream));
-      ctx->pending.push_back({a, b, launches, bytes});
-      if (ctx->pending.size() > 4096) resolve_pending(ctx);
-    } else {
-      ctx->filt_launches += launches;
-      ctx->filt_bytes += bytes;
-    }
-  }
-};
-
-evk::Csr to_csr(const evsl_csr_t *A) {
-  evk::Csr c;
-  c.n = (int)A->n;
-  c.nnz = A->nnz;
-  c.rp = A->row_ptr;
-  c.ci = A->col;
-  c.va = A->val;
-  c.dtype = A->dtype;
-  return c;
-}
-
-void check_csr(const evsl_csr_t *A) {
-  if (!A || A->n <= 0 || A->n >= (int64_t)1 << 31 || A->nnz < 0 || !A->row_ptr || !A->col ||
-      !A->val || (A->dtype != EVSL_F64 && A->dtype != EVSL_F32))
-    fail(EVSL_EINVAL);
-}
-
-// Algorithmic bytes of one filter step over nc columns (value size s):
-// the matrix once, plus P passes over the n x nc vectors.
-double step_bytes(const evsl_csr_t *A, int nc, int s, int passes) {
-  const double ma = (double)A->nnz * (s + 4) + 4.0 * (double)(A->n + 1);
-  return ma + (double)passes * (double)A->n * nc * s;
-}
-
-int pick_variant(evsl_ctx_t ctx) { return ctx->spmv_variant == 0 ? 3 : ctx->spmv_variant; }
 
 // --------------------------------------------------------------------------
 // Orthogonalisation helpers on a column-major basis B (n x *, leading dim ld).
@@ -525,8 +339,16 @@ struct Slice {
     }
     if (!end_cycle && ((i + 1) - l) % ncycle == 0) {
       const int k = i + 1;
-      std::vector<double> T = build_T(k), w(k);
-      evh::sym_eig(k, T.data(), w.data(), nullptr);
+      std::vector<double> w(k);
+      if (l == 0) {
+        // no thick-restart block: T is tridiagonal, O(k^2) without vectors
+        std::vector<double> d(alpha.begin(), alpha.begin() + k), e(std::max(k - 1, 1), 0.0);
+        std::copy(beta.begin(), beta.begin() + (k - 1), e.begin());
+        evh::tridiag_eig(k, d.data(), e.data(), w.data(), nullptr);
+      } else {
+        std::vector<double> T = build_T(k);
+        evh::sym_eig(k, T.data(), w.data(), nullptr);
+      }
       t_old = t_new;
       t_new = 0.0;
       for (double x : w)
@@ -584,18 +406,30 @@ struct Slice {
   void extract_nr(int dim) {
     Uc = (double *)ws(ctx, 40, sizeof(double) * ld * cmax);
     AUc = (double *)ws(ctx, 41, sizeof(double) * ld * cmax);
-    std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
-    evh::sym_eig(dim, T.data(), w.data(), Y.data());
+    // T is tridiagonal (no restart): eigenvalues by QR, then eigenvectors of
+    // the candidates (Ritz values >= bar) only, by inverse iteration
+    std::vector<double> d(alpha.begin(), alpha.begin() + dim), e(std::max(dim - 1, 1), 0.0), w(dim);
+    std::copy(beta.begin(), beta.begin() + (dim - 1), e.begin());
+    {
+      std::vector<double> d2(d), e2(e);
+      evh::tridiag_eig(dim, d2.data(), e2.data(), w.data(), nullptr);
+    }
+    int first = dim;
+    while (first > 0 && w[first - 1] >= bar) --first;
+    const int nc_all = dim - first;
+    std::vector<double> Zc((size_t)dim * std::max(nc_all, 1));
+    if (nc_all > 0) evh::tridiag_eigvecs(dim, d.data(), e.data(), nc_all, w.data() + first, Zc.data());
+    // candidates largest first; column t of Y below is eigenvector cand[t]
     std::vector<int> cand;
-    for (int j = dim - 1; j >= 0 && w[j] >= bar; --j) cand.push_back(j);
+    for (int j = dim - 1; j >= first; --j) cand.push_back(j);
+    auto Ycol = [&](int j) { return Zc.begin() + (size_t)(j - first) * dim; };
     const evk::Csr Ac = to_csr(A);
     int nacc = 0;
     for (size_t c0 = 0; c0 < cand.size() && status == EVSL_OK; c0 += cmax) {
       const int lc = (int)std::min<size_t>(cmax, cand.size() - c0);
       std::vector<double> Yh((size_t)dim * lc);
       for (int t = 0; t < lc; ++t)
-        std::copy(Y.begin() + (size_t)cand[c0 + t] * dim,
-                  Y.begin() + (size_t)cand[c0 + t] * dim + dim, Yh.begin() + (size_t)t * dim);
+        std::copy(Ycol(cand[c0 + t]), Ycol(cand[c0 + t]) + dim, Yh.begin() + (size_t)t * dim);
       HC(ctx, hipMemcpyAsync(Yc, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice,
                              st()));
       evk::gemm_nn(st(), n, dim, lc, col(0), ld, Yc, dim, Uc, ld);
@@ -1012,18 +846,6 @@ const char *evsl_strerror(int code) {
   }
 }
 
-#define EVSL_GUARD_BEGIN try {
-#define EVSL_GUARD_END                \
-  }                                   \
-  catch (const Error &e) {            \
-    return e.code;                    \
-  }                                   \
-  catch (const std::bad_alloc &) {    \
-    return EVSL_ENOMEM;               \
-  }                                   \
-  catch (...) {                       \
-    return EVSL_EINVAL;               \
-  }
 
 int evsl_create(evsl_ctx_t *ctx, void *stream) {
   if (!ctx) return EVSL_EINVAL;

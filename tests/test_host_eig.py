@@ -1,0 +1,77 @@
+"""The library's host eigensolvers (dense symmetric QR, tridiagonal QR and
+inverse iteration), built with g++ from the library sources and checked
+against numpy on random and clustered matrices."""
+import ctypes as C
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1802_05215_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    out = os.path.join(tempfile.mkdtemp(), "libhosteig.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC,
+                    os.path.join(CSRC, "host_eig.cpp"),
+                    os.path.join(ROOT, "tests", "native", "host_eig_shim.cpp"), "-o", out],
+                   check=True)
+    L = C.CDLL(out)
+    dp = C.POINTER(C.c_double)
+    L.t_sym_eig.argtypes = [C.c_int, dp, dp, dp]
+    L.t_tridiag_eig.argtypes = [C.c_int, dp, dp, dp, dp]
+    L.t_tridiag_eigvecs.argtypes = [C.c_int, dp, dp, C.c_int, dp, dp]
+    L.t_tridiag_eigvecs.restype = None
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tridiag(rng, m, clusters=False):
+    if clusters:
+        # block-diagonal copies of one tridiagonal: every eigenvalue repeated
+        k = m // 2
+        d0 = rng.standard_normal(k)
+        e0 = rng.standard_normal(k - 1)
+        d = np.concatenate([d0, d0])
+        e = np.concatenate([e0, [0.0], e0])
+        return d, e
+    return rng.standard_normal(m), rng.standard_normal(m - 1)
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 60])
+def test_sym_eig_matches_numpy(lib, m):
+    rng = np.random.default_rng(m)
+    M = rng.standard_normal((m, m))
+    M = (M + M.T) / 2
+    A = np.asfortranarray(M.copy())
+    w = np.empty(m)
+    V = np.empty((m, m), order="F")
+    lib.t_sym_eig(m, _p(A), _p(w), _p(V))
+    assert np.abs(w - np.linalg.eigvalsh(M)).max() <= 1e-12 * max(1, np.abs(w).max())
+    assert np.abs(M @ V - V * w).max() <= 1e-11
+    assert np.abs(V.T @ V - np.eye(m)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("m,clusters", [(50, False), (400, False), (300, True)])
+def test_tridiag_eig_and_inverse_iteration(lib, m, clusters):
+    rng = np.random.default_rng(m + clusters)
+    d, e = _tridiag(rng, m, clusters)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    ref = np.linalg.eigvalsh(T)
+    w = np.empty(m)
+    lib.t_tridiag_eig(m, _p(d.copy()), _p(np.concatenate([e, [0.0]])), _p(w), None)
+    assert np.abs(w - ref).max() <= 1e-12 * np.abs(ref).max()
+    # eigenvectors of the upper third of the spectrum
+    sel = w[2 * m // 3:].copy()
+    Z = np.empty((len(sel), m))
+    lib.t_tridiag_eigvecs(m, _p(d), _p(np.concatenate([e, [0.0]])), len(sel), _p(sel), _p(Z))
+    Z = Z.T
+    assert np.abs(T @ Z - Z * sel).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(Z.T @ Z - np.eye(len(sel))).max() <= 1e-10

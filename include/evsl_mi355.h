@@ -37,7 +37,9 @@ extern "C" {
 #define EVSL_EHIP 3      /* HIP runtime error (the hipError_t is kept in the context) */
 #define EVSL_EDEGREE 4   /* filter needs more than max_deg; the max_deg filter is returned */
 #define EVSL_ENOCONV 5   /* Lanczos step cap reached; the pairs locked so far are returned */
-#define EVSL_ESPECTRUM 6 /* filter blow-up: [lambda_min, lambda_max] misses part of the spectrum */
+#define EVSL_ESPECTRUM 6 /* filter blow-up: [lambda_min, lambda_max] misses part of the spectrum
+                            (a Ritz value of p(A-hat) exceeds sum |coef_j|, the bound of |p| on
+                            [-1, 1], or a non-finite value appears) */
 #define EVSL_ENOTIMPL 7  /* option not implemented */
 
 /* ---- value types ---- */

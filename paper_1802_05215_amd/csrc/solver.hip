@@ -65,7 +65,14 @@ struct Slice {
   double tlo, thi, lmin, lmax, normA, cc, dd, bar;
   int deg;
   std::vector<double> coef;
+  // |p(t)| <= sum |coef_j| on [-1, 1]: a Ritz value of the filtered operator
+  // beyond it means the spectrum leaves [lambda_min, lambda_max]
+  double pbound = 0.0;
   double *coef_dev = nullptr;
+  void check_filtered(const std::vector<double> &w) const {
+    for (double x : w)
+      if (!(std::fabs(x) <= 1.01 * pbound + 1e-12)) fail(EVSL_ESPECTRUM);
+  }
   // options
   int m, max_its, ncycle, nev_cap;
   double tol;
@@ -144,6 +151,8 @@ struct Slice {
     bar = pol->bar;
     deg = pol->deg;
     coef.assign(pol->coef, pol->coef + deg + 1);
+    pbound = 0.0;
+    for (double c : coef) pbound += std::fabs(c);
     const int nev_est = (opt && opt->nev_est > 0) ? opt->nev_est : 50;
     if (opt && opt->method != EVSL_LAN_TR && opt->method != EVSL_LAN_NR) fail(EVSL_EINVAL);
     nr = opt && opt->method == EVSL_LAN_NR;
@@ -349,6 +358,7 @@ struct Slice {
         std::vector<double> T = build_T(k);
         evh::sym_eig(k, T.data(), w.data(), nullptr);
       }
+      check_filtered(w);
       t_old = t_new;
       t_new = 0.0;
       for (double x : w)
@@ -414,6 +424,7 @@ struct Slice {
       std::vector<double> d2(d), e2(e);
       evh::tridiag_eig(dim, d2.data(), e2.data(), w.data(), nullptr);
     }
+    check_filtered(w);
     int first = dim;
     while (first > 0 && w[first - 1] >= bar) --first;
     const int nc_all = dim - first;
@@ -477,6 +488,7 @@ struct Slice {
     const double lock_tol = prec == EVSL_F32 ? std::max(tol, tol_lo) : tol;
     std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
     evh::sym_eig(dim, T.data(), w.data(), Y.data());
+    check_filtered(w);
     const double beta_last = next_ok ? beta[dim - 1] : 0.0;
     // candidates: Ritz values >= bar, largest first
     std::vector<int> cand;

@@ -38,6 +38,7 @@ struct SiSlice {
   double tlo = 0, thi = 0, normA = 0, cc = 0, dd = 0, bar = 0;
   int deg = 0;
   std::vector<double> coef;
+  double pbound = 0.0;  // |p(t)| <= sum |coef_j| on [-1, 1]
   int b = 0, max_its = 0;
   double tol = 0;
   uint64_t seed = 0;
@@ -80,6 +81,8 @@ struct SiSlice {
     bar = pol->bar;
     deg = pol->deg;
     coef.assign(pol->coef, pol->coef + deg + 1);
+    pbound = 0.0;
+    for (double c : coef) pbound += std::fabs(c);
     const int nev_est = (opt && opt->nev_est > 0) ? opt->nev_est : 50;
     b = (opt && opt->block > 0) ? opt->block : 3 * nev_est + 8;
     b = std::min(b, n);
@@ -165,6 +168,9 @@ struct SiSlice {
       int nin = 0, nconv = 0, bad = 0;
       for (int j = 0; j < b; ++j) {
         mu[j] = hbuf[j];
+        // a filter Rayleigh quotient beyond the bound of p on [-1, 1]: the
+        // spectrum leaves [lambda_min, lambda_max]
+        if (!(std::fabs(mu[j]) <= 1.01 * pbound + 1e-12)) fail(EVSL_ESPECTRUM);
         if (th[j] < tlo || th[j] > thi) continue;
         nin++;
         if (rs[j] <= tol)

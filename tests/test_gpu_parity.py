@@ -475,3 +475,19 @@ def test_fp32_batch_matches_fp64_batch(ctx):
         assert r32.max() <= 1e-8 and s32["status"] == 0, s32
         assert np.abs(l32 - l64).max() <= 1e-10 * 13
         assert np.abs(l32 - want).max() <= 1e-10 * 13
+
+
+def test_bounds_below_the_spectrum_are_detected(ctx):
+    """lambda_max = 11.65 for the 12^3 Laplacian; with b = 10.5 the filter grows
+    without bound above b, and every solver reports EVSL_ESPECTRUM."""
+    A = I.laplacian(12, 3)
+    Ad = ev.DeviceCsr.from_host(A)
+    intv = [1.0, 1.5, 0.0, 10.5]
+    p = _pol(intv)
+    for call in (lambda: ev.evsl_filtered_lanczos(ctx, Ad, intv, p, ev.lan_opts(nev_est=40)),
+                 lambda: ev.evsl_filtered_lanczos(ctx, Ad, intv, p,
+                                                  ev.lan_opts(nev_est=40, method=ev.EVSL_LAN_NR)),
+                 lambda: ev.evsl_filtered_subspace(ctx, Ad, intv, p, ev.si_opts(nev_est=40))):
+        with pytest.raises(ev.EvslError) as e:
+            call()
+        assert e.value.code == ev.EVSL_ESPECTRUM

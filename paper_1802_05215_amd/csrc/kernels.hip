@@ -589,6 +589,11 @@ void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, dou
 static constexpr int GEMV_RPL = 16;
 static constexpr int GEMV_ROWS = 64 * GEMV_RPL;
 
+// grid.x: 1024-row chunks; grid.y: groups of GEMV_COLS columns, so that small
+// n still fills the device. Per column a lane sums its rows in increasing
+// order and the wave reduces by a fixed butterfly.
+static constexpr int GEMV_COLS = 64;
+
 __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const double *__restrict__ B,
                                                         int64_t ld, const double *__restrict__ z,
                                                         double *partial) {
@@ -601,7 +606,8 @@ __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const dou
     zr[t] = r < n ? z[r] : 0.0;
   }
   const int nwg = gridDim.x;
-  for (int j = wave; j < nb; j += 4) {
+  const int jend = min(nb, (int)(blockIdx.y + 1) * GEMV_COLS);
+  for (int j = blockIdx.y * GEMV_COLS + wave; j < jend; j += 4) {
     const double *b = B + (int64_t)j * ld;
     double acc = 0.0;
 #pragma unroll
@@ -620,7 +626,8 @@ void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const dou
             double *partial, double *h) {
   if (nb <= 0 || n <= 0) return;
   const int nwg = (n + GEMV_ROWS - 1) / GEMV_ROWS;
-  hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg), dim3(TPB), 0, s, n, nb, B, ld, z, partial);
+  hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg, (nb + GEMV_COLS - 1) / GEMV_COLS), dim3(TPB), 0, s,
+                     n, nb, B, ld, z, partial);
   reduce_partials(s, nwg, nb, partial, 1.0, h);
 }
 

@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -314,6 +316,9 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
   std::vector<int> act;
   std::vector<double> tab;
   std::vector<int> ncs(kmax + 2);
+  const char *prog_env = std::getenv("EVSL_PROGRESS");
+  const bool progress = prog_env && std::atoi(prog_env) > 0;
+  int iteration = 0;
   while (true) {
     act.clear();
     for (int q : order)
@@ -364,6 +369,13 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
       sl[q].t_mv += tf;
       sl[q].after_filter();
       if (sl[q].done) sl[q].t_done = now_s() - t0;
+    }
+    ++iteration;
+    if (progress) {
+      int ndone = 0;
+      for (auto &x : sl) ndone += x.done ? 1 : 0;
+      std::fprintf(stderr, "[evsl] subspace iteration %d: %d columns filtered, %d of %d slices done, %.1f s\n",
+                   iteration, nc, ndone, nslices, now_s() - t0);
     }
   }
   int rc = EVSL_OK;

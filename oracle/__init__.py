@@ -88,6 +88,13 @@ def _setup(L):
     L.or_filtered_lanczos.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
                                       C.POINTER(LanOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
     L.or_filtered_lanczos_nr.argtypes = L.or_filtered_lanczos.argtypes
+    L.or_lanczos_dos.argtypes = [C.c_int64, _ip, _ip, _dp, C.c_int, C.c_int, C.c_uint64, _dp, _dp,
+                                 _ip]
+    L.or_lanczos_count.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                   C.c_double, C.c_double]
+    L.or_lanczos_count.restype = C.c_double
+    L.or_lanczos_slicer.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, C.c_int, _dp]
     L.or_filtered_subspace.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
                                        C.POINTER(SiOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
 
@@ -306,3 +313,32 @@ def filtered_subspace(A, intv, pol, block=None, max_its=200, tol=1e-10, seed=2, 
     k = st.nev
     stats = dict(nev=k, niter=st.niter, nmv=st.nmv, status=st.status)
     return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats
+
+
+def lanczos_dos(A, m, nvec, seed=1):
+    """Lanczos DOS quadrature: (nodes, weights, dims), nodes/weights nvec x m."""
+    rp, ci, va = (np.ascontiguousarray(A.row_ptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+                  _f64(A.val))
+    nodes = np.zeros((nvec, m))
+    weights = np.zeros((nvec, m))
+    dims = np.zeros(nvec, np.int32)
+    if lib().or_lanczos_dos(A.n, _i(rp), _i(ci), _d(va), m, nvec, seed, _d(nodes), _d(weights),
+                            _i(dims)) != 0:
+        raise ValueError("lanczos_dos: invalid arguments")
+    return nodes, weights, dims
+
+
+def lanczos_count(q, n, sigma, x0, x1):
+    nodes, weights, dims = q
+    nvec, m = nodes.shape
+    return lib().or_lanczos_count(_d(nodes), _d(weights), _i(dims), nvec, m, n, sigma, x0, x1)
+
+
+def lanczos_slicer(q, n, sigma, xi, eta, nslices, npts=2000):
+    nodes, weights, dims = q
+    nvec, m = nodes.shape
+    sli = np.empty(nslices + 1)
+    if lib().or_lanczos_slicer(_d(nodes), _d(weights), _i(dims), nvec, m, n, sigma, xi, eta,
+                               nslices, npts, _d(sli)) != 0:
+        raise ValueError("lanczos_slicer failed")
+    return sli

@@ -940,3 +940,95 @@ int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const 
   free(V); free(W); free(AQ); free(H); free(S); free(th); free(rs); free(mu); free(h); free(z);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Lanczos DOS with Gaussian quadrature (Section 2.1). The paper cites the
+ * method without formulas; the quadrature is the classical one (Golub and
+ * Meurant): nodes = eigenvalues of T_m, weights = squared first eigenvector
+ * components. */
+int or_lanczos_dos(int64_t n, const int32_t *rp, const int32_t *ci, const double *va, int m,
+                   int nvec, uint64_t seed, double *nodes, double *weights, int *dims) {
+  if (m < 1 || nvec < 1) return -1;
+  if (m > n) m = (int)n;
+  double *Q = (double *)calloc((size_t)n * (m + 1), sizeof(double));
+  double *z = (double *)malloc(sizeof(double) * n);
+  double *h = (double *)malloc(sizeof(double) * (m + 1));
+  double *al = (double *)malloc(sizeof(double) * m);
+  double *be = (double *)malloc(sizeof(double) * m);
+  double *T = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *Y = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *w = (double *)malloc(sizeof(double) * m);
+  for (int l = 0; l < nvec; ++l) {
+    or_lanczos_start(seed, n, l, Q);
+    double nq = nrm2(n, Q);
+    for (int64_t i = 0; i < n; ++i) Q[i] /= nq;
+    int dim = m;
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double *qi = Q + (size_t)i * n;
+      or_spmv(n, rp, ci, va, qi, z);
+      al[i] = dot(n, qi, z);
+      for (int64_t r = 0; r < n; ++r) z[r] -= al[i] * qi[r] + (i > 0 ? be[i - 1] * qi[r - n] : 0.0);
+      cgs_dgks(n, z, Q, i + 1, NULL, 0, h);
+      be[i] = nrm2(n, z);
+      scale = fmax(scale, fabs(al[i]) + (i > 0 ? be[i - 1] : 0.0));
+      if (i + 1 < m && be[i] <= 1e-12 * scale) { dim = i + 1; break; }
+      if (i + 1 < m)
+        for (int64_t r = 0; r < n; ++r) Q[(size_t)(i + 1) * n + r] = z[r] / be[i];
+    }
+    for (int j = 0; j < dim * dim; ++j) T[j] = 0.0;
+    for (int i = 0; i < dim; ++i) {
+      T[i + (size_t)i * dim] = al[i];
+      if (i + 1 < dim) T[i + (size_t)(i + 1) * dim] = T[(i + 1) + (size_t)i * dim] = be[i];
+    }
+    or_jacobi_eig(dim, T, w, Y);
+    for (int k = 0; k < m; ++k) {
+      nodes[(size_t)l * m + k] = k < dim ? w[k] : 0.0;
+      weights[(size_t)l * m + k] = k < dim ? Y[(size_t)k * dim] * Y[(size_t)k * dim] : 0.0;
+    }
+    dims[l] = dim;
+  }
+  free(Q); free(z); free(h); free(al); free(be); free(T); free(Y); free(w);
+  return 0;
+}
+
+double or_lanczos_count(const double *nodes, const double *weights, const int *dims, int nvec,
+                        int m, int64_t n, double sigma, double x0, double x1) {
+  double s = 0.0;
+  for (int l = 0; l < nvec; ++l)
+    for (int k = 0; k < dims[l]; ++k) {
+      const double t = nodes[(size_t)l * m + k], wk = weights[(size_t)l * m + k];
+      if (sigma > 0.0) {
+        const double r = 1.0 / (sigma * sqrt(2.0));
+        s += wk * 0.5 * (erf((x1 - t) * r) - erf((x0 - t) * r));
+      } else if (t >= x0 && t <= x1) {
+        s += wk;
+      }
+    }
+  return (double)n * s / nvec;
+}
+
+int or_lanczos_slicer(const double *nodes, const double *weights, const int *dims, int nvec,
+                      int m, int64_t n, double sigma, double xi, double eta, int nslices,
+                      int npts, double *sli) {
+  if (nslices < 1 || npts < nslices + 1 || !(eta > xi)) return -1;
+  double *C = (double *)malloc(sizeof(double) * npts);
+  for (int j = 0; j < npts; ++j) {
+    double x = xi + (eta - xi) * (double)j / (double)(npts - 1);
+    C[j] = or_lanczos_count(nodes, weights, dims, nvec, m, n, sigma, xi, x);
+  }
+  double total = C[npts - 1];
+  sli[0] = xi;
+  sli[nslices] = eta;
+  int prev = 0, rc = 0;
+  for (int i = 1; i < nslices; ++i) {
+    double target = total * (double)i / (double)nslices;
+    int j = prev + 1;
+    while (j < npts - 1 && C[j] < target) ++j;
+    if (j >= npts - 1) { rc = -1; break; }
+    sli[i] = xi + (eta - xi) * (double)j / (double)(npts - 1);
+    prev = j;
+  }
+  free(C);
+  return rc;
+}

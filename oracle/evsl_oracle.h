@@ -125,6 +125,27 @@ int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, cons
                            const or_lan_opts *opt, double *lam, double *res, double *Y,
                            or_lan_stats *st);
 
+/* Lanczos DOS (landos; Section 2.1: a Lanczos procedure with the related
+ * Gaussian quadrature, and the solver list of Section 3.1). For probe
+ * l = 0..nvec-1, m Lanczos steps with full reorthogonalisation from the
+ * Lanczos start vector of stream (seed, block l) give T_m; its eigenvalues
+ * are the quadrature nodes and the squared first components of its
+ * eigenvectors the weights (they sum to 1), so that
+ * sum_k w_k f(theta_k) = v^T f(A) v / v^T v exactly for polynomials f of degree
+ * < 2m. nodes/weights: nvec x m row-major, row l holding dims[l] <= m entries
+ * (fewer at an invariant subspace), the rest 0. */
+int or_lanczos_dos(int64_t n, const int32_t *rp, const int32_t *ci, const double *va, int m,
+                   int nvec, uint64_t seed, double *nodes, double *weights, int *dims);
+/* Estimated count in [x0, x1] from the quadrature: n / nvec times the sum of
+ * the weights of the nodes inside, each node spread by a Gaussian of standard
+ * deviation sigma (sigma = 0: a point mass). */
+double or_lanczos_count(const double *nodes, const double *weights, const int *dims, int nvec,
+                        int m, int64_t n, double sigma, double x0, double x1);
+/* Slicer on the Lanczos count (spslicer2), the same grid rule as or_slicer. */
+int or_lanczos_slicer(const double *nodes, const double *weights, const int *dims, int nvec,
+                      int m, int64_t n, double sigma, double xi, double eta, int nslices,
+                      int npts, double *sli);
+
 typedef struct {
   int block;      /* subspace dimension b */
   int max_its;    /* cap on iterations */

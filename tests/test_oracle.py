@@ -486,6 +486,65 @@ def test_filtered_subspace_boundary_empty_and_small_block():
     assert len(lam) == 0 and st["status"] == 0
 
 
+# ---------------------------------------------------------------- Lanczos DOS
+def test_lanczos_dos_gauss_quadrature_is_exact_to_degree_2m_minus_1():
+    """For each probe v, sum_k w_k T_j(theta_k-hat) = v^T T_j(A-hat) v / v^T v for
+    j < 2m (Gauss quadrature), with v the Lanczos start vector of its stream and
+    the right side computed densely."""
+    A = I.laplacian(12, 2, pot_seed=2)
+    D = A.to_dense()
+    m, nvec = 8, 3
+    nodes, weights, dims = oracle.lanczos_dos(A, m, nvec, seed=5)
+    w = np.linalg.eigvalsh(D)
+    c, d = 0.5 * (w[-1] + w[0]) + 0.0, 0.5 * (w[-1] - w[0]) * 1.001
+    Dh = (D - c * np.eye(A.n)) / d
+    for l in range(nvec):
+        assert dims[l] == m and abs(weights[l].sum() - 1.0) <= 1e-14
+        v = I.lanczos_start(5, A.n, l)
+        v = v / np.linalg.norm(v)
+        th = (nodes[l] - c) / d
+        t_prev, t_cur = v.copy(), Dh @ v
+        q_prev, q_cur = np.ones(m), th.copy()
+        for j in range(2 * m):
+            if j == 0:
+                lhs, rhs = weights[l].sum(), v @ v
+            elif j == 1:
+                lhs, rhs = weights[l] @ q_cur, v @ t_cur
+            else:
+                t_prev, t_cur = t_cur, 2 * Dh @ t_cur - t_prev
+                q_prev, q_cur = q_cur, 2 * th * q_cur - q_prev
+                lhs, rhs = weights[l] @ q_cur, v @ t_cur
+            assert abs(lhs - rhs) <= 1e-12, (l, j, lhs, rhs)
+
+
+def test_lanczos_dos_full_length_gives_the_spectrum():
+    """With m = n the nodes are the eigenvalues and the weights the squared
+    components of the start vector along the eigenvectors (numpy eigh)."""
+    A = I.laplacian(7, 2, pot_seed=3)
+    w, U = np.linalg.eigh(A.to_dense())
+    nodes, weights, dims = oracle.lanczos_dos(A, A.n, 1, seed=9)
+    assert dims[0] == A.n
+    v = I.lanczos_start(9, A.n, 0)
+    v = v / np.linalg.norm(v)
+    assert np.abs(nodes[0] - w).max() <= 1e-12 * np.abs(w).max()
+    assert np.abs(weights[0] - (U.T @ v) ** 2).max() <= 1e-10
+
+
+def test_lanczos_dos_count_and_slicer_against_closed_form():
+    A = I.laplacian(40, 2)
+    q = oracle.lanczos_dos(A, 60, 40, seed=1)
+    assert abs(oracle.lanczos_count(q, A.n, 0.0, -1.0, 9.0) - A.n) <= 1e-9
+    exact = lap_count(40, 2, 1.0, 1.6)
+    assert abs(oracle.lanczos_count(q, A.n, 0.0, 1.0, 1.6) - exact) <= 0.08 * exact
+    assert abs(oracle.lanczos_count(q, A.n, 0.05, 1.0, 1.6) - exact) <= 0.08 * exact
+    # slices of the 49^3 interval of Table tab:lapslicing hold similar closed-form counts
+    B = I.laplacian(20, 3)
+    qb = oracle.lanczos_dos(B, 80, 30, seed=2)
+    sli = oracle.lanczos_slicer(qb, B.n, 0.02, 1.0, 3.0, 5)
+    cnt = [lap_count(20, 3, sli[i], sli[i + 1]) for i in range(5)]
+    assert max(cnt) <= 1.35 * min(cnt), (sli, cnt)
+
+
 def test_paper_counts_from_closed_form():
     for r in GOLD["lap_problems"]["rows"]:
         if r["n"] > 600000:

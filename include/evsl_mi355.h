@@ -178,6 +178,27 @@ int evsl_slice_spectrum(const double *moments, int degree, int damping, const do
 int evsl_kpm_count(const double *moments, int degree, int damping, double lmin, double lmax,
                    double x0, double x1, double *count);
 
+/* ---- 2b. Lanczos DOS and its slicer (landos / spslicer2; Section 2.1: a
+ * Lanczos procedure with the related Gaussian quadrature; Section 3.1) ----
+ * For probe l = 0..nvec-1: msteps Lanczos steps with full reorthogonalisation
+ * (fewer at an invariant subspace, dims[l] < msteps) from the Lanczos start
+ * vector of stream (seed, block l); the eigenvalues of T are the quadrature
+ * nodes and the squared first components of its eigenvectors the weights
+ * (summing to 1 per probe). nodes, weights: host, nvec x msteps row-major,
+ * unused entries 0; dims: host, nvec. Synchronous. */
+int evsl_lanczos_dos(evsl_ctx_t ctx, const evsl_csr_t *A, int msteps, int nvec, uint64_t seed,
+                     double *nodes, double *weights, int *dims);
+/* Host-only. Estimated count in [x0, x1]: n / nvec times the quadrature weight
+ * inside, each node spread by a Gaussian of standard deviation sigma (0: a
+ * point mass). */
+int evsl_lanczos_count(const double *nodes, const double *weights, const int *dims, int nvec,
+                       int msteps, int64_t n, double sigma, double x0, double x1, double *count);
+/* Host-only. Cuts [xi, eta] into nslices pieces of equal estimated count on an
+ * npts-point grid (the rule of evsl_slice_spectrum); sli gets nslices+1 points. */
+int evsl_slice_spectrum_lanczos(const double *nodes, const double *weights, const int *dims,
+                                int nvec, int msteps, int64_t n, double sigma, double xi,
+                                double eta, int nslices, int npts, double *sli);
+
 /* ---- 3. filter coefficients (find_pol, Section 2.2.1: eq:mapping, eq:Cheb0,
  * eq:mu, eq:Neq, eq:polPJ) ----
  * Host-only. intv = {t_i, t_{i+1}, lambda_min, lambda_max}. The degree is the
@@ -292,6 +313,11 @@ int evsl_mem_stats(evsl_ctx_t ctx, int64_t *current, int64_t *peak, int reset_pe
 int evsl_copy_probe(evsl_ctx_t ctx, int64_t bytes, int reps, double *seconds_per_copy);
 /* Enables (1) or disables (0) HIP-event timing of each filter application. */
 int evsl_set_timing(evsl_ctx_t ctx, int on);
+/* Enables (1, the default) or disables (0) HIP graphs in evsl_filtered_lanczos_batch:
+ * each group's filter (gather, one launch per degree step, scatter) is captured
+ * once per active set and replayed every Lanczos step. Results are identical
+ * either way (same kernels, same order). */
+int evsl_set_graphs(evsl_ctx_t ctx, int on);
 /* Selects the kernel for single-vector filter steps: 0 auto, 1 direct
  * row-per-thread, 2 LDS-staged CSR stream, 3 LDS-staged with the nonzero loop
  * unrolled by 8 and XCD-contiguous workgroup order, 4 as 3 without the XCD

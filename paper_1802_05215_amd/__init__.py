@@ -31,6 +31,7 @@ EXPORTS = [
     "evsl_filter_stats", "evsl_reset_stats", "evsl_set_timing", "evsl_set_spmv_variant",
     "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
     "evsl_gram", "evsl_mem_stats", "evsl_filtered_subspace", "evsl_filtered_subspace_batch",
+    "evsl_set_graphs", "evsl_lanczos_dos", "evsl_lanczos_count", "evsl_slice_spectrum_lanczos",
 ]
 
 
@@ -110,6 +111,15 @@ def _lib():
         L.evsl_filter_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), _dp, _dp]
         L.evsl_reset_stats.argtypes = [C.c_void_p]
         L.evsl_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.evsl_set_graphs.argtypes = [C.c_void_p, C.c_int]
+        _ip = C.POINTER(C.c_int)
+        L.evsl_lanczos_dos.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int, C.c_uint64,
+                                       _dp, _dp, _ip]
+        L.evsl_lanczos_count.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                         C.c_double, C.c_double, _dp]
+        L.evsl_slice_spectrum_lanczos.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64,
+                                                  C.c_double, C.c_double, C.c_double, C.c_int,
+                                                  C.c_int, _dp]
         L.evsl_set_spmv_variant.argtypes = [C.c_void_p, C.c_int]
         L.evsl_set_block_variant.argtypes = [C.c_int]
         L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int,
@@ -186,6 +196,9 @@ class Ctx:
 
     def set_timing(self, on):
         _chk(_lib().evsl_set_timing(self.h, int(bool(on))), "set_timing")
+
+    def set_graphs(self, on):
+        _chk(_lib().evsl_set_graphs(self.h, int(bool(on))), "set_graphs")
 
     def set_spmv_variant(self, v):
         _chk(_lib().evsl_set_spmv_variant(self.h, int(v)), "set_spmv_variant")
@@ -275,6 +288,42 @@ def evsl_kpm_count(moments, damping, lmin, lmax, x0, x1):
     _chk(_lib().evsl_kpm_count(_dptr(mom), len(mom) - 1, damping, lmin, lmax, x0, x1,
                                C.byref(out)), "evsl_kpm_count")
     return out.value
+
+
+def evsl_lanczos_dos(ctx, A, msteps, nvec, seed=1):
+    """Lanczos DOS quadrature: (nodes, weights, dims), nodes/weights nvec x msteps."""
+    nodes = np.zeros((nvec, msteps))
+    weights = np.zeros((nvec, msteps))
+    dims = np.zeros(nvec, np.int32)
+    _chk(_lib().evsl_lanczos_dos(ctx.h, C.byref(A.t), msteps, nvec, seed, _dptr(nodes),
+                                 _dptr(weights), dims.ctypes.data_as(C.POINTER(C.c_int))),
+         "evsl_lanczos_dos")
+    return nodes, weights, dims
+
+
+def evsl_lanczos_count(q, n, sigma, x0, x1):
+    nodes, weights, dims = (np.ascontiguousarray(q[0], np.float64),
+                            np.ascontiguousarray(q[1], np.float64),
+                            np.ascontiguousarray(q[2], np.int32))
+    out = C.c_double()
+    _chk(_lib().evsl_lanczos_count(_dptr(nodes), _dptr(weights),
+                                   dims.ctypes.data_as(C.POINTER(C.c_int)), nodes.shape[0],
+                                   nodes.shape[1], int(n), sigma, x0, x1, C.byref(out)),
+         "evsl_lanczos_count")
+    return out.value
+
+
+def evsl_slice_spectrum_lanczos(q, n, sigma, xi, eta, nslices, npts=2000):
+    nodes, weights, dims = (np.ascontiguousarray(q[0], np.float64),
+                            np.ascontiguousarray(q[1], np.float64),
+                            np.ascontiguousarray(q[2], np.int32))
+    sli = np.empty(nslices + 1)
+    _chk(_lib().evsl_slice_spectrum_lanczos(_dptr(nodes), _dptr(weights),
+                                            dims.ctypes.data_as(C.POINTER(C.c_int)),
+                                            nodes.shape[0], nodes.shape[1], int(n), sigma, xi, eta,
+                                            nslices, npts, _dptr(sli)),
+         "evsl_slice_spectrum_lanczos")
+    return sli
 
 
 class Pol:

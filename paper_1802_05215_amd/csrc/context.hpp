@@ -37,6 +37,8 @@ struct evsl_ctx_s {
   int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged, 3/4 unrolled
   int group_width = 0;   // columns per block filter launch in batches (0: all)
   bool timing = true;
+  bool use_graphs = true;  // batch group filters replayed from HIP graphs
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
   // filter measurement
   int64_t filt_launches = 0;
   double filt_seconds = 0.0;
@@ -179,6 +181,12 @@ struct FilterTimer {
     }
   }
 };
+
+// The context's capture stream (non-blocking, default priority).
+inline hipStream_t capture_stream(evsl_ctx_t ctx) {
+  if (!ctx->cap_stream) HC(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  return ctx->cap_stream;
+}
 
 inline evk::Csr to_csr(const evsl_csr_t *A) {
   evk::Csr c;

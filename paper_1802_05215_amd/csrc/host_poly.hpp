@@ -1,5 +1,6 @@
 // Host-side polynomial work: damping, find_pol, KPM count, slicer.
 #pragma once
+#include <cstdint>
 
 namespace evh {
 
@@ -20,6 +21,15 @@ double kpm_count(int K, const double *mom, const double *g, double c, double d, 
                  double x1);
 int slice(int K, const double *mom, int damp, const double intv[4], int nslices, int npts,
           double *sli);
+// Count in [x0, x1] from a Gaussian quadrature of the spectral density (nvec
+// probes, nodes/weights nvec x m row-major, dims[l] valid entries per row):
+// n / nvec times the weight inside, each node spread by a Gaussian of standard
+// deviation sigma (0: a point mass).
+double quad_count(const double *nodes, const double *weights, const int *dims, int nvec, int m,
+                  int64_t n, double sigma, double x0, double x1);
+// Equal-count slicing of [xi, eta] on that count (npts-point grid).
+int quad_slice(const double *nodes, const double *weights, const int *dims, int nvec, int m,
+               int64_t n, double sigma, double xi, double eta, int nslices, int npts, double *sli);
 
 // Symmetric eigen-decomposition of the m x m column-major A (overwritten):
 // Householder tridiagonalisation, then implicit QR steps with Wilkinson

@@ -883,6 +883,7 @@ int evsl_destroy(evsl_ctx_t ctx) {
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   for (void *p : ctx->ws_ptr) dfree(ctx, p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return EVSL_OK;
 }
@@ -894,6 +895,12 @@ int evsl_mem_stats(evsl_ctx_t ctx, int64_t *current, int64_t *peak, int reset_pe
   if (current) *current = ctx->mem_cur;
   if (peak) *peak = ctx->mem_peak;
   if (reset_peak) ctx->mem_peak = ctx->mem_cur;
+  return EVSL_OK;
+}
+
+int evsl_set_graphs(evsl_ctx_t ctx, int on) {
+  if (!ctx) return EVSL_EINVAL;
+  ctx->use_graphs = on != 0;
   return EVSL_OK;
 }
 
@@ -1147,14 +1154,17 @@ int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int 
   EVSL_GUARD_END
 }
 
-int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64_t seed,
-                         double *lmin, double *lmax) {
-  if (!ctx || !lmin || !lmax || nsteps < 1) return EVSL_EINVAL;
-  EVSL_GUARD_BEGIN
-  check_csr(A);
-  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+}  // extern "C"
+
+namespace {
+
+// m Lanczos steps with full reorthogonalisation (two CGS passes) from the
+// start vector of stream (seed, block): alpha[i] = hs[2i], beta[i+1] =
+// hs[2i+1]. Stops early at an invariant subspace (beta <= 1e-12 of the
+// running scale); returns the dimension reached.
+int lanczos_tridiag(evsl_ctx_t ctx, const evsl_csr_t *A, int m, uint64_t seed, int64_t block,
+                    std::vector<double> &alpha, std::vector<double> &beta) {
   const int n = (int)A->n;
-  const int m = (int)std::min<int64_t>(nsteps, n);
   const int64_t ld = ((int64_t)n + 63) / 64 * 64;
   hipStream_t s = ctx->stream;
   double *Q = (double *)ws(ctx, 0, sizeof(double) * ld * (m + 1));
@@ -1168,7 +1178,7 @@ int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64
   ow.scal = (double *)ws(ctx, 6, sizeof(double) * (2 * m + 8));
   double *hs = pinned(ctx, 2 * m + 8);
   const evk::Csr Ac = to_csr(A);
-  evk::lanczos_start(s, n, seed, 0, z);
+  evk::lanczos_start(s, n, seed, block, z);
   evk::col_dots(s, n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
   evk::normalize(s, n, z, Q, ow.nrm2, nullptr);
   int dim = m;
@@ -1199,20 +1209,86 @@ int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64
     }
   }
   HC(ctx, hipStreamSynchronize(s));
+  alpha.assign(dim, 0.0);
+  beta.assign(dim, 0.0);
+  for (int t = 0; t < dim; ++t) {
+    alpha[t] = hs[2 * t];
+    beta[t] = hs[2 * t + 1];
+  }
+  return dim;
+}
+
+}  // namespace
+
+extern "C" {
+
+int evsl_spectrum_bounds(evsl_ctx_t ctx, const evsl_csr_t *A, int nsteps, uint64_t seed,
+                         double *lmin, double *lmax) {
+  if (!ctx || !lmin || !lmax || nsteps < 1) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const int m = (int)std::min<int64_t>(nsteps, A->n);
+  std::vector<double> al, be;
+  const int dim = lanczos_tridiag(ctx, A, m, seed, 0, al, be);
   std::vector<double> T((size_t)dim * dim, 0.0), w(dim), Y((size_t)dim * dim);
   for (int t = 0; t < dim; ++t) {
-    T[t + (size_t)t * dim] = hs[2 * t];
+    T[t + (size_t)t * dim] = al[t];
     if (t + 1 < dim) {
-      T[t + (size_t)(t + 1) * dim] = hs[2 * t + 1];
-      T[(t + 1) + (size_t)t * dim] = hs[2 * t + 1];
+      T[t + (size_t)(t + 1) * dim] = be[t];
+      T[(t + 1) + (size_t)t * dim] = be[t];
     }
   }
   evh::sym_eig(dim, T.data(), w.data(), Y.data());
-  const double blast = hs[2 * (dim - 1) + 1];
+  const double blast = be[dim - 1];
   *lmin = w[0] - std::fabs(blast * Y[(dim - 1) + 0]);
   *lmax = w[dim - 1] + std::fabs(blast * Y[(dim - 1) + (size_t)(dim - 1) * dim]);
   return EVSL_OK;
   EVSL_GUARD_END
+}
+
+int evsl_lanczos_dos(evsl_ctx_t ctx, const evsl_csr_t *A, int msteps, int nvec, uint64_t seed,
+                     double *nodes, double *weights, int *dims) {
+  if (!ctx || msteps < 1 || nvec < 1 || !nodes || !weights || !dims) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const int m = (int)std::min<int64_t>(msteps, A->n);
+  std::vector<double> al, be;
+  for (int l = 0; l < nvec; ++l) {
+    const int dim = lanczos_tridiag(ctx, A, m, seed, l, al, be);
+    // quadrature: eigenvalues of T, squared first components of its eigenvectors
+    std::vector<double> V((size_t)dim * dim, 0.0), w(dim), e(std::max(dim - 1, 1), 0.0);
+    for (int i = 0; i < dim; ++i) V[i + (size_t)i * dim] = 1.0;
+    for (int i = 0; i + 1 < dim; ++i) e[i] = be[i];
+    evh::tridiag_eig(dim, al.data(), e.data(), w.data(), V.data());
+    for (int k = 0; k < msteps; ++k) {
+      nodes[(size_t)l * msteps + k] = k < dim ? w[k] : 0.0;
+      weights[(size_t)l * msteps + k] = k < dim ? V[(size_t)k * dim] * V[(size_t)k * dim] : 0.0;
+    }
+    dims[l] = dim;
+  }
+  return EVSL_OK;
+  EVSL_GUARD_END
+}
+
+int evsl_lanczos_count(const double *nodes, const double *weights, const int *dims, int nvec,
+                       int msteps, int64_t n, double sigma, double x0, double x1, double *count) {
+  if (!nodes || !weights || !dims || nvec < 1 || msteps < 1 || n < 1 || sigma < 0 || !count)
+    return EVSL_EINVAL;
+  *count = evh::quad_count(nodes, weights, dims, nvec, msteps, n, sigma, x0, x1);
+  return EVSL_OK;
+}
+
+int evsl_slice_spectrum_lanczos(const double *nodes, const double *weights, const int *dims,
+                                int nvec, int msteps, int64_t n, double sigma, double xi,
+                                double eta, int nslices, int npts, double *sli) {
+  if (!nodes || !weights || !dims || nvec < 1 || msteps < 1 || n < 1 || sigma < 0 || !sli)
+    return EVSL_EINVAL;
+  return evh::quad_slice(nodes, weights, dims, nvec, msteps, n, sigma, xi, eta, nslices, npts,
+                         sli) == 0
+             ? EVSL_OK
+             : EVSL_EINVAL;
 }
 
 int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
@@ -1381,6 +1457,38 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   std::vector<int> act, prev_act;
   std::vector<double> tab;
   std::vector<int> ncs(kmax + 2);
+  // One HIP graph per group (gather, the degree-step launches, scatter): the
+  // buffers, pointer arrays and coefficient table are fixed while the active
+  // set is, so each Lanczos step replays the graphs; they are rebuilt when a
+  // slice finishes. The per-step column pointers are uploaded before replay.
+  struct GroupGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    double bytes = 0.0;
+  };
+  struct Graphs {
+    std::vector<GroupGraph> v;
+    void clear() {
+      for (auto &e : v) {
+        if (e.x) (void)hipGraphExecDestroy(e.x);
+        if (e.g) (void)hipGraphDestroy(e.g);
+      }
+      v.clear();
+    }
+    ~Graphs() { clear(); }
+  } graphs;
+  // ends a capture left open by an error, so the stream stays usable
+  struct CaptureGuard {
+    hipStream_t s;
+    bool open = false;
+    ~CaptureGuard() {
+      if (open) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+      }
+    }
+  };
   while (true) {
     act.clear();
     for (int q : order)
@@ -1401,6 +1509,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
         ncs[j] = std::max(a, 1);
       }
       prev_act = act;
+      graphs.clear();
     }
     // filter the current Lanczos vectors of the active slices, group by group
     // (consecutive slices in degree order; one block launch per degree step)
@@ -1428,29 +1537,54 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       double **gp = ptrs + 2 * g0;
       HC(ctx, hipMemcpyAsync(gp, hg, sizeof(double *) * 2 * gn, hipMemcpyHostToDevice, s));
       const double *gtab = ctab + (size_t)g0 * (km + 1);
-      auto run_group = [&](auto tag, const evk::Csr &Ag) {
+      hipStream_t ls = s;  // the stream the group's launches go to (or are captured on)
+      auto run_group = [&](auto tag, const evk::Csr &Ag) -> double {
         using T = decltype(tag);
+        double gbytes = 0.0;
         T *x0 = (T *)X0, *x1 = (T *)X1, *yb = (T *)Yb;
-        evk::gather_cols<T>(s, n, gn, (const double *const *)gp, x0, gn);
-        evk::cheb_blk<T>(s, Ag, evk::STEP_FIRST, 1.0 / dd, -cc / dd, x0, nullptr, x1, yb, gn,
+        evk::gather_cols<T>(ls, n, gn, (const double *const *)gp, x0, gn);
+        evk::cheb_blk<T>(ls, Ag, evk::STEP_FIRST, 1.0 / dd, -cc / dd, x0, nullptr, x1, yb, gn,
                          std::min(gn, std::max(ncs[1] - g0, 1)), gtab, km + 1, 1, nullptr,
                          nullptr);
-        bytes += step_bytes(A, gn, es, 3);
+        gbytes += step_bytes(A, gn, es, 3);
         // x0 = W_0, x1 = W_1; W_{j+1} is written over W_{j-1}
         T *wprev = x0, *wcur = x1;
         for (int j = 1; j < gk; ++j) {
           const int ncj = std::min(gn, std::max(ncs[j + 1] - g0, 1));
-          evk::cheb_blk<T>(s, Ag, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev, yb,
+          evk::cheb_blk<T>(ls, Ag, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev, yb,
                            gn, ncj, gtab, km + 1, j + 1, nullptr, nullptr);
-          bytes += step_bytes(A, ncj, es, 5);
+          gbytes += step_bytes(A, ncj, es, 5);
           std::swap(wprev, wcur);
         }
-        evk::scatter_cols<T>(s, n, gn, yb, gn, (double *const *)(gp + gn));
+        evk::scatter_cols<T>(ls, n, gn, yb, gn, (double *const *)(gp + gn));
+        return gbytes;
       };
-      if (prec == EVSL_F32)
-        run_group(float(), sl[act[g0]].csr32());
-      else
-        run_group(double(), Ac);
+      auto launch_group = [&]() -> double {
+        return prec == EVSL_F32 ? run_group(float(), sl[act[g0]].csr32())
+                                : run_group(double(), Ac);
+      };
+      if (ctx->use_graphs) {
+        const size_t gi = (size_t)(g0 / gw);
+        if (graphs.v.size() <= gi) graphs.v.resize(gi + 1);
+        GroupGraph &G = graphs.v[gi];
+        if (!G.x) {
+          // captured on the context's own capture stream (the caller's stream
+          // may be the null stream, which cannot capture), replayed on s
+          ls = capture_stream(ctx);
+          CaptureGuard cg{ls};
+          HC(ctx, hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+          cg.open = true;
+          G.bytes = launch_group();
+          cg.open = false;
+          HC(ctx, hipStreamEndCapture(ls, &G.g));
+          HC(ctx, hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0));
+          ls = s;
+        }
+        HC(ctx, hipGraphLaunch(G.x, s));
+        bytes += G.bytes;
+      } else {
+        bytes += launch_group();
+      }
       launches += gk;
     }
     for (int q : act) HC(ctx, hipEventRecord(sl[q].ev1, s));

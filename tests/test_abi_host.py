@@ -102,3 +102,21 @@ def test_slicer_errors():
         ev.evsl_slice_spectrum(mom, 2, [1.0, 0.5, 0.0, 8.0], 3)
     with pytest.raises(ev.EvslError):
         ev.evsl_slice_spectrum(mom, 2, [0.0, 1.0, 0.0, 8.0], 10, npts=8)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.03])
+def test_lanczos_count_and_slicer_match_oracle(sigma):
+    """Host-only quadrature count and slicer of the library against the
+    oracle's, on a quadrature the oracle computed (40x40 Laplacian)."""
+    import evsl_inputs as I
+    A = I.laplacian(40, 2)
+    q = oracle.lanczos_dos(A, 40, 12, seed=4)
+    for x0, x1 in ((1.0, 1.6), (0.0, 8.0), (2.5, 2.51), (-1.0, 0.5)):
+        want = oracle.lanczos_count(q, A.n, sigma, x0, x1)
+        got = ev.evsl_lanczos_count(q, A.n, sigma, x0, x1)
+        assert abs(got - want) <= 1e-11 * A.n
+    got = ev.evsl_slice_spectrum_lanczos(q, A.n, sigma, 1.0, 3.0, 6)
+    want = oracle.lanczos_slicer(q, A.n, sigma, 1.0, 3.0, 6)
+    assert np.array_equal(got, want)
+    with pytest.raises(ev.EvslError):
+        ev.evsl_lanczos_count(q, A.n, -1.0, 0.0, 1.0)

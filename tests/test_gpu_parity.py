@@ -340,6 +340,43 @@ def test_batch_slices_match_single_and_closed_form(ctx, group):
     ctx.set_group_width(0)
 
 
+@pytest.mark.parametrize("group,own_stream", [(0, False), (2, False), (2, True)])
+def test_batch_graph_replays_equal_eager_launches(ctx, group, own_stream):
+    """The batch driver replays each group's filter from a HIP graph every
+    Lanczos step (with the step's eager orthogonalisation and host
+    synchronisation between replays); the results must equal, bit for bit,
+    those of the same launches issued eagerly. Checked on the null stream and
+    on a stream of its own, with one group of three slices and with groups of
+    two and one (the single-slice group stays eager)."""
+    A = I.laplacian(24, 2, pot_seed=1)
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    cuts = [1.0, 1.3, 1.6, 1.9]
+    ivs = [[cuts[q], cuts[q + 1], lo, hi] for q in range(3)]
+    pols = [_pol(iv) for iv in ivs]
+    opts = [ev.lan_opts(tol=1e-10, seed=2 + q, nev_est=40) for q in range(3)]
+    stream = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        c = ev.Ctx(stream) if own_stream else ctx
+        Ad = ev.DeviceCsr.from_host(A)
+        stream.synchronize()
+        c.set_group_width(group)
+        res = {}
+        for on in (False, True, True):
+            c.set_graphs(on)
+            outs = ev.evsl_filtered_lanczos_batch(c, Ad, ivs, pols, opts)
+            res.setdefault(on, []).append(
+                [(lam, r, Y.cpu().numpy(), st["niter"]) for lam, Y, r, st in outs])
+        c.set_graphs(True)
+        c.set_group_width(0)
+        if own_stream:
+            c.close()
+    eager = res[False][0]
+    for run in res[True]:
+        for (l0, r0, y0, n0), (l1, r1, y1, n1) in zip(eager, run):
+            assert n0 == n1
+            assert np.array_equal(l0, l1) and np.array_equal(r0, r1) and np.array_equal(y0, y1)
+
+
 def test_autotune_picks_a_width_and_batches_still_agree(ctx):
     A = I.laplacian(30, 3, pot_seed=0)
     Ad = ev.DeviceCsr.from_host(A)
@@ -491,3 +528,23 @@ def test_bounds_below_the_spectrum_are_detected(ctx):
         with pytest.raises(ev.EvslError) as e:
             call()
         assert e.value.code == ev.EVSL_ESPECTRUM
+
+
+@pytest.mark.parametrize("N,dim,pot", [(40, 2, None), (16, 3, 0)])
+def test_lanczos_dos_matches_oracle(ctx, N, dim, pot):
+    """Quadrature nodes, weights and counts of the device Lanczos DOS against
+    the oracle's on the same probes; nodes to 1e-10 ||A||, counts to 1e-8 n."""
+    A = I.laplacian(N, dim, pot_seed=pot)
+    Ad = ev.DeviceCsr.from_host(A)
+    m, nvec = 40, 6
+    q = ev.evsl_lanczos_dos(ctx, Ad, m, nvec, seed=3)
+    oq = oracle.lanczos_dos(A, m, nvec, seed=3)
+    assert np.array_equal(q[2], oq[2])
+    normA = np.abs(oq[0]).max()
+    assert np.abs(q[0] - oq[0]).max() <= 1e-10 * normA
+    assert np.abs(q[1].sum(axis=1) - 1.0).max() <= 1e-13
+    for x0, x1 in ((1.0, 1.6), (0.5, 3.0), (4.0, 20.0)):
+        for sigma in (0.0, 0.05):
+            a = ev.evsl_lanczos_count(q, A.n, sigma, x0, x1)
+            b = oracle.lanczos_count(oq, A.n, sigma, x0, x1)
+            assert abs(a - b) <= 1e-8 * A.n, (x0, x1, sigma, a, b)

@@ -44,6 +44,9 @@ def parse():
                          "number (replaces --interval)")
     ap.add_argument("--slices", type=int, nargs="+", default=None,
                     help="solve only these slices of the KPM cut (default: all)")
+    ap.add_argument("--dos", choices=["kpm", "lanczos"], default="kpm",
+                    help="density estimate for slicing: KPM moments or Lanczos quadrature "
+                         "(--kpm-degree steps, --kpm-vectors probes)")
     ap.add_argument("--kpm-degree", type=int, default=80)
     ap.add_argument("--kpm-vectors", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -97,24 +100,33 @@ def one_step(ctx, ev, Ad, args):
     intv = [xi, eta, lo, hi]
     mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, args.kpm_degree, args.kpm_vectors, seed=1,
                                damping=ev.DAMP_JACKSON)
+    if args.dos == "lanczos":
+        quad = ev.evsl_lanczos_dos(ctx, Ad, args.kpm_degree, args.kpm_vectors, seed=1)
+        count = lambda x0, x1: ev.evsl_lanczos_count(quad, Ad.n, 0.0, x0, x1)
+    else:
+        count = lambda x0, x1: ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, x0, x1)
     if args.interval_count > 0:
         # eta where the estimated count from lambda_min reaches interval_count
         a, b = lo, hi
         for _ in range(60):
             mid = 0.5 * (a + b)
-            if ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, lo, mid) < args.interval_count:
+            if count(lo, mid) < args.interval_count:
                 a = mid
             else:
                 b = mid
         eta = 0.5 * (a + b)
         intv = [lo, eta, lo, hi]
-        est = ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, lo, eta)
-    sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, args.nslices, 2000)
+        est = count(lo, eta)
+    if args.dos == "lanczos":
+        est = count(intv[0], intv[1])
+        sli = ev.evsl_slice_spectrum_lanczos(quad, Ad.n, 0.0, intv[0], intv[1], args.nslices, 2000)
+    else:
+        sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, args.nslices, 2000)
     sel = args.slices if args.slices else list(range(args.nslices))
     ivs, pols, opts = [], [], []
     for q in sel:
         iv = [sli[q], sli[q + 1], lo, hi]
-        cnt = ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, sli[q], sli[q + 1])
+        cnt = count(sli[q], sli[q + 1])
         ivs.append(iv)
         pols.append(ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON, tau=0.8, tau_ext=0.4))
         nev_est = max(int(cnt * 1.1) + 5, 10)
@@ -566,8 +578,11 @@ def main():
                 f"all eigenpairs in [{rec['interval'][0]:.6g}, {rec['interval'][1]:.6g}]"
                 + (f" (lambda_min to the KPM count {args.interval_count})"
                    if args.interval_count > 0 else "")
-                + f", {args.nslices} KPM slices (degree {args.kpm_degree}, {args.kpm_vectors} "
-                f"vectors), Jackson filters, {solver}, tol {args.tol:g}, {arith}, "
+                + (f", {args.nslices} KPM slices (degree {args.kpm_degree}, "
+                   f"{args.kpm_vectors} vectors)" if args.dos == "kpm" else
+                   f", {args.nslices} Lanczos-DOS slices ({args.kpm_degree} steps, "
+                   f"{args.kpm_vectors} probes)")
+                + f", Jackson filters, {solver}, tol {args.tol:g}, {arith}, "
                 f"slices {args.mode}"
                 + (f"; only slices {args.slices} of the cut solved" if args.slices else ""))
     out = {

@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--dos", choices=["kpm", "lanczos"], default="kpm",
                     help="density estimate for slicing: KPM moments or Lanczos quadrature "
                          "(--kpm-degree steps, --kpm-vectors probes)")
+    ap.add_argument("--dos-sigma", type=float, default=0.0,
+                    help="Lanczos DOS: Gaussian spread of each quadrature node "
+                         "(0: (lambda_max - lambda_min) / (2 steps))")
     ap.add_argument("--kpm-degree", type=int, default=80)
     ap.add_argument("--kpm-vectors", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -102,7 +105,10 @@ def one_step(ctx, ev, Ad, args):
                                damping=ev.DAMP_JACKSON)
     if args.dos == "lanczos":
         quad = ev.evsl_lanczos_dos(ctx, Ad, args.kpm_degree, args.kpm_vectors, seed=1)
-        count = lambda x0, x1: ev.evsl_lanczos_count(quad, Ad.n, 0.0, x0, x1)
+        # the quadrature has m nodes per probe: spread each over the spacing of
+        # m points on the spectrum, so the count is smooth enough to cut
+        sigma = args.dos_sigma or (hi - lo) / (2 * args.kpm_degree)
+        count = lambda x0, x1: ev.evsl_lanczos_count(quad, Ad.n, sigma, x0, x1)
     else:
         count = lambda x0, x1: ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, x0, x1)
     if args.interval_count > 0:
@@ -119,7 +125,8 @@ def one_step(ctx, ev, Ad, args):
         est = count(lo, eta)
     if args.dos == "lanczos":
         est = count(intv[0], intv[1])
-        sli = ev.evsl_slice_spectrum_lanczos(quad, Ad.n, 0.0, intv[0], intv[1], args.nslices, 2000)
+        sli = ev.evsl_slice_spectrum_lanczos(quad, Ad.n, sigma, intv[0], intv[1], args.nslices,
+                                             2000)
     else:
         sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, args.nslices, 2000)
     sel = args.slices if args.slices else list(range(args.nslices))

@@ -545,6 +545,20 @@ def test_lanczos_dos_count_and_slicer_against_closed_form():
     assert max(cnt) <= 1.35 * min(cnt), (sli, cnt)
 
 
+def test_lanczos_dos_smoothed_slices_balance_closed_form_counts():
+    """Point masses give a step-function count that cannot be cut finely;
+    spreading each node by sigma = (b - a) / (2m) balances ten slices of a
+    300-eigenvalue-per-slice interval to within 35% (closed-form counts)."""
+    A = I.laplacian(200, 2)
+    q = oracle.lanczos_dos(A, 80, 20, seed=1)
+    sli = oracle.lanczos_slicer(q, A.n, 8.0 / 160, 1.0, 1.3, 10)
+    cnt = [lap_count(200, 2, sli[i], sli[i + 1]) for i in range(10)]
+    assert max(cnt) <= 1.35 * min(cnt), cnt
+    raw = oracle.lanczos_slicer(q, A.n, 0.0, 1.0, 1.3, 10)
+    cnt0 = [lap_count(200, 2, raw[i], raw[i + 1]) for i in range(10)]
+    assert max(cnt0) > 5 * max(min(cnt0), 1)
+
+
 def test_paper_counts_from_closed_form():
     for r in GOLD["lap_problems"]["rows"]:
         if r["n"] > 600000:

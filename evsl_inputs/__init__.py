@@ -133,3 +133,34 @@ def lanczos_start(seed: int, n: int, restart: int = 0) -> np.ndarray:
     Not normalised."""
     idx = np.uint64(restart) * np.uint64(n) + np.arange(n, dtype=np.uint64)
     return 2.0 * uniform01(seed, idx) - 1.0
+
+
+def fe_pencil(N: int) -> tuple:
+    """Bilinear finite-element pencil on an N x N interior grid of the unit
+    square (Dirichlet), without the mesh factors: stiffness
+    A = K1 (x) M1 + M1 (x) K1 and mass B = M1 (x) M1 with K1 = tridiag(-1, 2, -1)
+    and M1 = tridiag(1, 4, 1) / 6 (both N x N). 9-point CSR, x fastest, columns
+    ascending; B is SPD with eigenvalues in (1/9, 1)."""
+    K1 = {-1: -1.0, 0: 2.0, 1: -1.0}
+    M1 = {-1: 1.0 / 6.0, 0: 4.0 / 6.0, 1: 1.0 / 6.0}
+    n = N * N
+    p = np.arange(n, dtype=np.int64)
+    ix, iy = p % N, p // N
+    cols, va, vb, mask = [], [], [], []
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            ok = (ix + dx >= 0) & (ix + dx < N) & (iy + dy >= 0) & (iy + dy < N)
+            cols.append(p + dy * N + dx)
+            # A = K1(x) M1(y) + M1(x) K1(y); B = M1(x) M1(y)
+            va.append(np.full(n, K1[dx] * M1[dy] + M1[dx] * K1[dy]))
+            vb.append(np.full(n, M1[dx] * M1[dy]))
+            mask.append(ok)
+    cols = np.stack(cols, axis=1)
+    va, vb, mask = np.stack(va, axis=1), np.stack(vb, axis=1), np.stack(mask, axis=1)
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = cols[mask].astype(np.int32)
+    A = CSR(n, row_ptr.astype(np.int32), col, va[mask].astype(np.float64), grid=N, dim=2)
+    B = CSR(n, row_ptr.astype(np.int32), col.copy(), vb[mask].astype(np.float64), grid=N, dim=2)
+    return A, B

@@ -88,6 +88,13 @@ def _setup(L):
     L.or_filtered_lanczos.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, C.c_int, _dp, C.c_double,
                                       C.POINTER(LanOpts), _dp, _dp, _dp, C.POINTER(LanStats)]
     L.or_filtered_lanczos_nr.argtypes = L.or_filtered_lanczos.argtypes
+    L.or_lspol.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, _dp]
+    L.or_cg_solve.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, _dp]
+    L.or_lanczos_bounds_gen.argtypes = [C.c_int64, _ip, _ip, _dp, _ip, _ip, _dp, C.c_int,
+                                        C.c_uint64, _dp, _dp]
+    L.or_filtered_lanczos_gen.argtypes = [C.c_int64, _ip, _ip, _dp, _ip, _ip, _dp, _dp, C.c_int, _dp,
+                                          C.c_double, C.POINTER(LanOpts), _dp, _dp, _dp,
+                                          C.POINTER(LanStats)]
     L.or_lanczos_dos.argtypes = [C.c_int64, _ip, _ip, _dp, C.c_int, C.c_int, C.c_uint64, _dp, _dp,
                                  _ip]
     L.or_lanczos_count.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
@@ -342,3 +349,62 @@ def lanczos_slicer(q, n, sigma, xi, eta, nslices, npts=2000):
                                nslices, npts, _d(sli)) != 0:
         raise ValueError("lanczos_slicer failed")
     return sli
+
+
+def _csr(A):
+    return (np.ascontiguousarray(A.row_ptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+            _f64(A.val))
+
+
+def lspol(kind, lo, hi, deg):
+    """Chebyshev coefficients of 1/t (kind 0) or 1/sqrt(t) (kind 1) on [lo, hi]."""
+    coef = np.zeros(deg + 1)
+    if lib().or_lspol(kind, lo, hi, deg, _d(coef)) != 0:
+        raise ValueError("lspol: invalid arguments")
+    return coef
+
+
+def cg_solve(B, r):
+    rp, ci, vb = _csr(B)
+    r = _f64(r)
+    x = np.empty_like(r)
+    lib().or_cg_solve(B.n, _i(rp), _i(ci), _d(vb), _d(r), _d(x))
+    return x
+
+
+def lanczos_bounds_gen(A, B, nsteps=80, seed=3):
+    ra, ca, va = _csr(A)
+    rb, cb, vb = _csr(B)
+    lo, hi = C.c_double(), C.c_double()
+    lib().or_lanczos_bounds_gen(A.n, _i(ra), _i(ca), _d(va), _i(rb), _i(cb), _d(vb), nsteps, seed,
+                                C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def filtered_lanczos_gen(A, B, intv, pol, m=None, ncycle=30, tol=1e-10, seed=2, nev_cap=None,
+                         nev_est=None):
+    """Filtered non-restart Lanczos for the pencil (A, B). Returns (lam, Y (n x nev,
+    B-orthonormal), res, stats)."""
+    if nev_est is None:
+        nev_est = 50
+    if m is None:
+        m = max(5 * int(nev_est) + 200, 400)
+    if nev_cap is None:
+        nev_cap = max(2 * int(nev_est) + 40, 100)
+    n = A.n
+    ra, ca, va = _csr(A)
+    rb, cb, vb = _csr(B)
+    iv = _f64(intv)
+    coef = _f64(pol["coef"])
+    lam, res = np.empty(nev_cap), np.empty(nev_cap)
+    Y = np.empty((nev_cap, n))
+    opts = LanOpts(m, m, ncycle, tol, seed, nev_cap)
+    st = LanStats()
+    rc = lib().or_filtered_lanczos_gen(n, _i(ra), _i(ca), _d(va), _i(rb), _i(cb), _d(vb), _d(iv),
+                                       len(coef) - 1, _d(coef), pol["bar"], C.byref(opts), _d(lam),
+                                       _d(res), _d(Y), C.byref(st))
+    if rc != 0:
+        raise ValueError("filtered_lanczos_gen: invalid arguments")
+    k = st.nev
+    stats = dict(nev=k, niter=st.niter, nmv=st.nmv, status=st.status)
+    return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats

@@ -1032,3 +1032,238 @@ int or_lanczos_slicer(const double *nodes, const double *weights, const int *dim
   free(C);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Generalized problems (Section 2.4). */
+int or_lspol(int kind, double lo, double hi, int deg, double *coef) {
+  if (!(hi > lo) || !(lo > 0.0) || deg < 0 || (kind != 0 && kind != 1)) return -1;
+  const int N = 1024;
+  const double c = 0.5 * (hi + lo), d = 0.5 * (hi - lo);
+  for (int j = 0; j <= deg; ++j) coef[j] = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double th = M_PI * (k + 0.5) / N;
+    const double t = c + d * cos(th);
+    const double f = kind == 0 ? 1.0 / t : 1.0 / sqrt(t);
+    for (int j = 0; j <= deg; ++j) coef[j] += f * cos(j * th);
+  }
+  for (int j = 0; j <= deg; ++j) coef[j] *= (j == 0 ? 1.0 : 2.0) / N;
+  return 0;
+}
+
+int or_cg_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *vb,
+                const double *r, double *x) {
+  double *res = (double *)malloc(sizeof(double) * n);
+  double *p = (double *)malloc(sizeof(double) * n);
+  double *q = (double *)malloc(sizeof(double) * n);
+  for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; res[i] = r[i]; p[i] = r[i]; }
+  const double r0 = nrm2(n, r);
+  double rr = dot(n, res, res);
+  int it = 0;
+  for (; it < 10000 && sqrt(rr) > 1e-15 * r0; ++it) {
+    or_spmv(n, rp, ci, vb, p, q);
+    const double a = rr / dot(n, p, q);
+    for (int64_t i = 0; i < n; ++i) { x[i] += a * p[i]; res[i] -= a * q[i]; }
+    const double rn = dot(n, res, res);
+    const double bb = rn / rr;
+    rr = rn;
+    for (int64_t i = 0; i < n; ++i) p[i] = res[i] + bb * p[i];
+  }
+  free(res); free(p); free(q);
+  return it;
+}
+
+/* B-orthonormal random start: w = v / ||v||_B, z = B w. */
+static void gen_start(int64_t n, const int32_t *rpb, const int32_t *cib, const double *vb,
+                      uint64_t seed, int64_t block, double *w, double *z) {
+  or_lanczos_start(seed, n, block, w);
+  or_spmv(n, rpb, cib, vb, w, z);
+  const double nb = sqrt(dot(n, w, z));
+  for (int64_t i = 0; i < n; ++i) { w[i] /= nb; z[i] /= nb; }
+}
+
+int or_lanczos_bounds_gen(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                          const int32_t *rpb, const int32_t *cib, const double *vb, int nsteps,
+                          uint64_t seed, double *lmin, double *lmax) {
+  int m = nsteps < n ? nsteps : (int)n;
+  if (m < 1) return -1;
+  double *W = (double *)calloc((size_t)n * (m + 1), sizeof(double));
+  double *Z = (double *)calloc((size_t)n * (m + 1), sizeof(double));
+  double *z = (double *)malloc(sizeof(double) * n);
+  double *T = (double *)calloc((size_t)m * m, sizeof(double));
+  double *h = (double *)malloc(sizeof(double) * (m + 1));
+  gen_start(n, rpb, cib, vb, seed, 0, W, Z);
+  double beta = 0.0, scale = 0.0;
+  int dim = m;
+  for (int i = 0; i < m; ++i) {
+    double *wi = W + (size_t)i * n, *zi = Z + (size_t)i * n;
+    /* Algorithm alg:LanAB, lines 3-10 */
+    or_spmv(n, rp, ci, va, wi, z);
+    if (i > 0)
+      for (int64_t r = 0; r < n; ++r) z[r] -= beta * Z[(size_t)(i - 1) * n + r];
+    const double alpha = dot(n, z, wi);
+    for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j <= i; ++j) h[j] = dot(n, z, W + (size_t)j * n);
+      for (int j = 0; j <= i; ++j)
+        for (int64_t r = 0; r < n; ++r) z[r] -= h[j] * Z[(size_t)j * n + r];
+    }
+    T[i + (size_t)i * m] = alpha;
+    double *wn = W + (size_t)(i + 1) * n;
+    or_cg_solve(n, rpb, cib, vb, z, wn);
+    scale = fmax(scale, fabs(alpha) + beta);
+    beta = sqrt(fmax(dot(n, wn, z), 0.0));
+    if (beta <= 1e-12 * scale) { dim = i + 1; beta = 0.0; break; }
+    for (int64_t r = 0; r < n; ++r) { wn[r] /= beta; Z[(size_t)(i + 1) * n + r] = z[r] / beta; }
+    if (i + 1 < m) T[i + (size_t)(i + 1) * m] = T[(i + 1) + (size_t)i * m] = beta;
+  }
+  double *Tm = (double *)malloc(sizeof(double) * dim * dim);
+  for (int j = 0; j < dim; ++j)
+    for (int i = 0; i < dim; ++i) Tm[i + (size_t)j * dim] = T[i + (size_t)j * m];
+  double *w = (double *)malloc(sizeof(double) * dim), *Y = (double *)malloc(sizeof(double) * dim * dim);
+  or_jacobi_eig(dim, Tm, w, Y);
+  *lmin = w[0] - fabs(beta * Y[(dim - 1) + 0]);
+  *lmax = w[dim - 1] + fabs(beta * Y[(dim - 1) + (size_t)(dim - 1) * dim]);
+  free(W); free(Z); free(z); free(T); free(h); free(Tm); free(w); free(Y);
+  return 0;
+}
+
+/* y = rho(A-hat B^(-1)) x by the Chebyshev recurrence in M = A-hat B^(-1):
+ * M v = (A u - c v)/d with u = B^(-1) v (exact solve). */
+static void gen_filter(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                       const int32_t *rpb, const int32_t *cib, const double *vb, double c,
+                       double d, int deg, const double *coef, const double *x, double *y) {
+  double *w0 = (double *)malloc(sizeof(double) * n), *w1 = (double *)malloc(sizeof(double) * n);
+  double *w2 = (double *)malloc(sizeof(double) * n), *u = (double *)malloc(sizeof(double) * n);
+  double *au = (double *)malloc(sizeof(double) * n);
+  memcpy(w0, x, sizeof(double) * n);
+  or_cg_solve(n, rpb, cib, vb, w0, u);
+  or_spmv(n, rp, ci, va, u, au);
+  for (int64_t i = 0; i < n; ++i) {
+    w1[i] = (au[i] - c * w0[i]) / d;
+    y[i] = coef[0] * w0[i] + coef[1] * w1[i];
+  }
+  for (int j = 1; j < deg; ++j) {
+    or_cg_solve(n, rpb, cib, vb, w1, u);
+    or_spmv(n, rp, ci, va, u, au);
+    for (int64_t i = 0; i < n; ++i) {
+      w2[i] = 2.0 * (au[i] - c * w1[i]) / d - w0[i];
+      y[i] += coef[j + 1] * w2[i];
+    }
+    double *t = w0; w0 = w1; w1 = w2; w2 = t;
+  }
+  free(w0); free(w1); free(w2); free(u); free(au);
+}
+
+int or_filtered_lanczos_gen(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                            const int32_t *rpb, const int32_t *cib, const double *vb,
+                            const double intv[4], int deg, const double *coef, double bar,
+                            const or_lan_opts *opt, double *lam, double *res, double *Y,
+                            or_lan_stats *st) {
+  memset(st, 0, sizeof(*st));
+  const double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  const double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
+  const double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
+  int m = opt->m;
+  if (m > n - 1) m = (int)(n - 1);
+  if (m < 2 || deg < 1 || opt->ncycle < 1) return -1;
+  const int M1 = m + 1;
+  double *W = (double *)calloc((size_t)n * M1, sizeof(double));
+  double *Z = (double *)calloc((size_t)n * M1, sizeof(double));
+  double *T = (double *)calloc((size_t)M1 * M1, sizeof(double));
+  double *Tw = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *w = (double *)malloc(sizeof(double) * m), *Yv = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *z = (double *)malloc(sizeof(double) * n), *x = (double *)malloc(sizeof(double) * n);
+  double *ax = (double *)malloc(sizeof(double) * n), *bx = (double *)malloc(sizeof(double) * n);
+  double *h = (double *)malloc(sizeof(double) * (M1 + 1));
+#define TT(i, j) T[(i) + (size_t)(j) * M1]
+  int its = 0, nmv = 0, status = 1, nev = 0, dim = m;
+  double t_old = NAN, t_new = NAN, beta = 0.0;
+  gen_start(n, rpb, cib, vb, opt->seed, 0, W, Z);
+  for (int i = 0; i < m; ++i) {
+    its++;
+    double *wi = W + (size_t)i * n, *zi = Z + (size_t)i * n;
+    /* eq:polyapp1: z = rho(A-hat B^(-1)) z_i - beta_i z_{i-1} */
+    gen_filter(n, rp, ci, va, rpb, cib, vb, cc, dd, deg, coef, zi, z);
+    nmv += deg;
+    if (i > 0)
+      for (int64_t r = 0; r < n; ++r) z[r] -= beta * Z[(size_t)(i - 1) * n + r];
+    const double alpha = dot(n, z, wi);
+    for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j <= i; ++j) h[j] = dot(n, z, W + (size_t)j * n);
+      for (int j = 0; j <= i; ++j)
+        for (int64_t r = 0; r < n; ++r) z[r] -= h[j] * Z[(size_t)j * n + r];
+    }
+    TT(i, i) = alpha;
+    double *wn = W + (size_t)(i + 1) * n;
+    or_cg_solve(n, rpb, cib, vb, z, wn);
+    beta = sqrt(fmax(dot(n, wn, z), 0.0));
+    if (beta <= 1e-12) { dim = i + 1; status = 0; break; }
+    for (int64_t r = 0; r < n; ++r) { wn[r] /= beta; Z[(size_t)(i + 1) * n + r] = z[r] / beta; }
+    TT(i, i + 1) = TT(i + 1, i) = beta;
+    if ((i + 1) % opt->ncycle == 0) {
+      const int k = i + 1;
+      for (int jj = 0; jj < k; ++jj)
+        for (int ii = 0; ii < k; ++ii) Tw[ii + (size_t)jj * k] = TT(ii, jj);
+      or_jacobi_eig(k, Tw, w, Yv);
+      t_old = t_new;
+      t_new = 0.0;
+      for (int jj = 0; jj < k; ++jj)
+        if (w[jj] >= bar) t_new += w[jj];
+      if (fabs(t_new - t_old) < 1e-10 * (fabs(t_new) > 1.0 ? fabs(t_new) : 1.0)) {
+        dim = k;
+        status = 0;
+        break;
+      }
+    }
+  }
+  for (int jj = 0; jj < dim; ++jj)
+    for (int ii = 0; ii < dim; ++ii) Tw[ii + (size_t)jj * dim] = TT(ii, jj);
+  or_jacobi_eig(dim, Tw, w, Yv);
+  for (int jj = dim - 1; jj >= 0 && w[jj] >= bar; --jj) {
+    const double *y = Yv + (size_t)jj * dim;
+    for (int64_t r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int p = 0; p < dim; ++p) s += W[(size_t)p * n + r] * y[p];
+      x[r] = s;
+    }
+    or_spmv(n, rp, ci, va, x, ax);
+    or_spmv(n, rpb, cib, vb, x, bx);
+    nmv++;
+    const double xbx = dot(n, x, bx), lam_j = dot(n, x, ax) / xbx;
+    if (lam_j < tlo || lam_j > thi) continue;
+    double rr = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+      const double e = ax[r] - lam_j * bx[r];
+      rr += e * e;
+    }
+    const double rj = sqrt(rr) / (nrm2(n, bx) * normA);
+    if (rj > opt->tol) continue;
+    if (nev >= opt->nev_cap) { status = 2; break; }
+    const double nb = sqrt(xbx);
+    for (int64_t r = 0; r < n; ++r) Y[(size_t)nev * n + r] = x[r] / nb;
+    lam[nev] = lam_j;
+    res[nev] = rj;
+    nev++;
+  }
+  for (int i = 0; i < nev - 1; ++i) {
+    int mi = i;
+    for (int j = i + 1; j < nev; ++j)
+      if (lam[j] < lam[mi]) mi = j;
+    if (mi != i) {
+      double t = lam[i]; lam[i] = lam[mi]; lam[mi] = t;
+      t = res[i]; res[i] = res[mi]; res[mi] = t;
+      memcpy(x, Y + (size_t)i * n, sizeof(double) * n);
+      memcpy(Y + (size_t)i * n, Y + (size_t)mi * n, sizeof(double) * n);
+      memcpy(Y + (size_t)mi * n, x, sizeof(double) * n);
+    }
+  }
+#undef TT
+  st->nev = nev;
+  st->niter = its;
+  st->nmv = nmv;
+  st->status = status;
+  free(W); free(Z); free(T); free(Tw); free(w); free(Yv); free(z); free(x); free(ax); free(bx);
+  free(h);
+  return 0;
+}

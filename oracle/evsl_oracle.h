@@ -146,6 +146,40 @@ int or_lanczos_slicer(const double *nodes, const double *weights, const int *dim
                       int m, int64_t n, double sigma, double xi, double eta, int nslices,
                       int npts, double *sli);
 
+/* ---- generalized problems A x = lambda B x, B SPD (Section 2.4, eq:stdB,
+ * Algorithm alg:LanAB; filtering through eq:gen1 and eq:polyapp1) ---- */
+
+/* Least-squares Chebyshev approximation on [lo, hi] (lsPol, Section 3.1: the
+ * polynomial approximations of t^(-1) and t^(-1/2) used for solves with B):
+ * kind 0: f(t) = 1/t, kind 1: f(t) = 1/sqrt(t); coef[0..deg] are the
+ * Chebyshev coefficients in u = (t - c)/d, c = (hi + lo)/2, d = (hi - lo)/2,
+ * from the Chebyshev-Gauss quadrature of f with 1024 nodes (the truncated
+ * Chebyshev series is the least-squares fit in the Chebyshev weight). */
+int or_lspol(int kind, double lo, double hi, int deg, double *coef);
+/* x = B^(-1) r by conjugate gradients to ||r - B x|| <= 1e-15 ||r||. */
+int or_cg_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *vb,
+                const double *r, double *x);
+/* Bounds of the pencil's spectrum: nsteps of Algorithm alg:LanAB (full
+ * reorthogonalisation, exact solves) from the Lanczos start vector of stream
+ * `seed`, widened by the extreme Ritz residual estimates. */
+int or_lanczos_bounds_gen(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                          const int32_t *rpb, const int32_t *cib, const double *vb, int nsteps,
+                          uint64_t seed, double *lmin, double *lmax);
+/* Filtered non-restart Lanczos for (A, B): Algorithm alg:LanAB applied to the
+ * pencil (B rho(B^(-1) A-hat), B) of eq:gen1, so that its line 3 is eq:polyapp1,
+ * z = rho(A-hat B^(-1)) z_i - beta_i z_{i-1} with A-hat = (A - cB)/d; the
+ * Chebyshev recurrence in A-hat B^(-1) needs one solve with B and one product
+ * with A per degree step (exact solves here). Stopping as
+ * or_filtered_lanczos_nr; Ritz vectors W_m y (eq:gen1), each checked by its
+ * Rayleigh quotient x^T A x / x^T B x and residual
+ * ||A x - lambda B x|| / (||B x|| max(|lambda_min|, |lambda_max|)). Y holds
+ * B-normalised vectors. */
+int or_filtered_lanczos_gen(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                            const int32_t *rpb, const int32_t *cib, const double *vb,
+                            const double intv[4], int deg, const double *coef, double bar,
+                            const or_lan_opts *opt, double *lam, double *res, double *Y,
+                            or_lan_stats *st);
+
 typedef struct {
   int block;      /* subspace dimension b */
   int max_its;    /* cap on iterations */

@@ -559,6 +559,70 @@ def test_lanczos_dos_smoothed_slices_balance_closed_form_counts():
     assert max(cnt0) > 5 * max(min(cnt0), 1)
 
 
+# ---------------------------------------------------------------- generalized problems
+def _fe_eigs(N):
+    th = np.arange(1, N + 1) * np.pi / (N + 1)
+    mu = (2 - 2 * np.cos(th)) / ((4 + 2 * np.cos(th)) / 6)
+    return np.sort((mu[:, None] + mu[None, :]).ravel())
+
+
+def test_fe_pencil_closed_form():
+    import scipy.linalg as sl
+    A, B = I.fe_pencil(9)
+    w = sl.eigh(A.to_dense(), B.to_dense(), eigvals_only=True)
+    assert np.abs(w - _fe_eigs(9)).max() <= 1e-12 * w.max()
+
+
+@pytest.mark.parametrize("lo,hi,deg", [(0.1, 1.0, 20), (1.0, 3.0, 12), (0.11, 0.99, 40)])
+def test_lspol_inverse_matches_closed_form_series(lo, hi, deg):
+    """1/(c + d u) = (2/sqrt(c^2 - d^2)) sum' (-r)^j T_j(u), r = (c - sqrt(c^2 - d^2))/d."""
+    c, d = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    q = np.sqrt(c * c - d * d)
+    r = (c - q) / d
+    ref = 2 * (-r) ** np.arange(deg + 1) / q
+    ref[0] /= 2
+    assert np.abs(oracle.lspol(0, lo, hi, deg) - ref).max() <= 1e-14 * ref[0]
+
+
+def test_lspol_inverse_sqrt_converges():
+    t = np.linspace(0.1, 1.0, 2001)
+    u = (t - 0.55) / 0.45
+    errs = []
+    for deg in (10, 20, 40):
+        cf = oracle.lspol(1, 0.1, 1.0, deg)
+        errs.append(np.abs(np.polynomial.chebyshev.chebval(u, cf) - 1 / np.sqrt(t)).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 1e-9, errs
+
+
+def test_cg_and_pencil_bounds():
+    A, B = I.fe_pencil(16)
+    r = I.lanczos_start(4, B.n)
+    x = oracle.cg_solve(B, r)
+    assert np.linalg.norm(B.to_dense() @ x - r) <= 1e-13 * np.linalg.norm(r)
+    ex = _fe_eigs(16)
+    lo, hi = oracle.lanczos_bounds_gen(A, B, 80, 3)
+    assert lo <= ex[0] + 1e-12 and hi >= ex[-1] - 1e-12
+    assert ex[0] - lo <= 1e-3 * ex[-1] and hi - ex[-1] <= 1e-3 * ex[-1]
+
+
+@pytest.mark.parametrize("ab", [(3.0, 5.0), (10.0, 11.0)])
+def test_filtered_lanczos_gen_fe_pencil_closed_form(ab):
+    A, B = I.fe_pencil(16)
+    ex = _fe_eigs(16)
+    want = ex[(ex >= ab[0]) & (ex <= ab[1])]
+    lo, hi = oracle.lanczos_bounds_gen(A, B, 80, 3)
+    intv = [ab[0], ab[1], lo, hi]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_JACKSON)
+    lam, Y, res, st = oracle.filtered_lanczos_gen(A, B, intv, p, tol=1e-10, nev_est=len(want))
+    assert st["status"] == 0 and len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-11 * ex[-1]
+    assert res.max() <= 1e-10
+    Db = B.to_dense()
+    assert np.abs(Y.T @ Db @ Y - np.eye(len(lam))).max() <= 1e-10
+    R = A.to_dense() @ Y - Db @ Y * lam
+    assert np.linalg.norm(R, axis=0).max() <= 1e-9 * ex[-1]
+
+
 def test_paper_counts_from_closed_form():
     for r in GOLD["lap_problems"]["rows"]:
         if r["n"] > 600000:

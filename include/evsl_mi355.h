@@ -268,6 +268,36 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
                                  const double *intv, const evsl_pol_t *pols,
                                  const evsl_si_opts_t *opts, evsl_eigs_t *outs);
 
+/* ---- 7. generalized problems A x = lambda B x, B SPD (Section 2.4; eq:stdB,
+ * Algorithm alg:LanAB; filtering through eq:gen1 and eq:polyapp1) ----
+ * Solves with B are the least-squares Chebyshev approximation of 1/t on
+ * [bbounds[0], bbounds[1]] (a range containing B's spectrum, bbounds[0] > 0,
+ * e.g. from evsl_spectrum_bounds on B) of degree bdeg (lsPol, Section 3.1);
+ * its error decays like ((sqrt(k) - 1)/(sqrt(k) + 1))^bdeg with
+ * k = bbounds[1]/bbounds[0]. */
+/* Host-only. Chebyshev coefficients (in u = (t - c)/d on [lo, hi]) of the
+ * least-squares approximation of 1/t (kind 0) or 1/sqrt(t) (kind 1). */
+int evsl_lspol(int kind, double lo, double hi, int deg, double *coef);
+/* Bounds of the pencil's spectrum from nsteps of Algorithm alg:LanAB (full
+ * reorthogonalisation) from the Lanczos start vector of stream `seed`, widened
+ * by the extreme Ritz residual estimates. Synchronous. */
+int evsl_spectrum_bounds_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_csr_t *B,
+                             const double bbounds[2], int bdeg, int nsteps, uint64_t seed,
+                             double *lmin, double *lmax);
+/* Filtered non-restart Lanczos for (A, B) on one slice: Algorithm alg:LanAB
+ * applied to (B rho(B^-1 A-hat), B), line 3 as eq:polyapp1 (per degree step one
+ * solve with B and one product with A), full reorthogonalisation, the settled
+ * sum test of EVSL_LAN_NR; intv = {t_i, t_{i+1}, lambda_min, lambda_max} of the
+ * pencil and pol from evsl_cheb_coeffs on it. opt as for the non-restart form
+ * (method EVSL_LAN_TR and prec EVSL_F32: EVSL_ENOTIMPL). Returns the Ritz pairs
+ * in the slice with ||A y - lambda B y|| / (||B y|| max(|lambda_min|,
+ * |lambda_max|)) <= tol; Y is B-orthonormal. out->nrestart counts the solves
+ * with B. Synchronous. */
+int evsl_filtered_lanczos_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_csr_t *B,
+                              const double bbounds[2], int bdeg, const double intv[4],
+                              const evsl_pol_t *pol, const evsl_lan_opts_t *opt,
+                              evsl_eigs_t *out);
+
 /* Copies the result vectors into a caller-owned device array dst (column j
  * of out->Y to dst + j*ldd, ldd >= n). Asynchronous on the context stream. */
 int evsl_eigs_get_vectors(evsl_ctx_t ctx, const evsl_eigs_t *out, int64_t n, double *dst,

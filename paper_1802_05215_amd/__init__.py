@@ -32,6 +32,7 @@ EXPORTS = [
     "evsl_set_block_variant", "evsl_autotune", "evsl_set_group_width", "evsl_copy_probe",
     "evsl_gram", "evsl_mem_stats", "evsl_filtered_subspace", "evsl_filtered_subspace_batch",
     "evsl_set_graphs", "evsl_lanczos_dos", "evsl_lanczos_count", "evsl_slice_spectrum_lanczos",
+    "evsl_lspol", "evsl_spectrum_bounds_gen", "evsl_filtered_lanczos_gen",
 ]
 
 
@@ -113,6 +114,12 @@ def _lib():
         L.evsl_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.evsl_set_graphs.argtypes = [C.c_void_p, C.c_int]
         _ip = C.POINTER(C.c_int)
+        L.evsl_lspol.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, _dp]
+        L.evsl_spectrum_bounds_gen.argtypes = [C.c_void_p, C.POINTER(CsrT), C.POINTER(CsrT), _dp,
+                                               C.c_int, C.c_int, C.c_uint64, _dp, _dp]
+        L.evsl_filtered_lanczos_gen.argtypes = [C.c_void_p, C.POINTER(CsrT), C.POINTER(CsrT), _dp,
+                                                C.c_int, _dp, C.POINTER(PolT),
+                                                C.POINTER(LanOptsT), C.POINTER(EigsT)]
         L.evsl_lanczos_dos.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int, C.c_uint64,
                                        _dp, _dp, _ip]
         L.evsl_lanczos_count.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
@@ -450,3 +457,32 @@ def evsl_filtered_subspace_batch(ctx, A, intvs, pols, opts_list):
     _chk(_lib().evsl_filtered_subspace_batch(ctx.h, C.byref(A.t), ns, _dptr(iv), parr, oarr, outs),
          "evsl_filtered_subspace_batch", ok=(EVSL_OK, EVSL_ENOCONV))
     return [_take(ctx, outs[q], A.n, A.val.device) for q in range(ns)]
+
+
+def evsl_lspol(kind, lo, hi, deg):
+    """Chebyshev coefficients of the least-squares fit of 1/t (kind 0) or
+    1/sqrt(t) (kind 1) on [lo, hi]."""
+    coef = np.zeros(deg + 1)
+    _chk(_lib().evsl_lspol(kind, lo, hi, deg, _dptr(coef)), "evsl_lspol")
+    return coef
+
+
+def evsl_spectrum_bounds_gen(ctx, A, B, bbounds, bdeg, nsteps=80, seed=3):
+    bb = _f64(bbounds)
+    lo, hi = C.c_double(), C.c_double()
+    _chk(_lib().evsl_spectrum_bounds_gen(ctx.h, C.byref(A.t), C.byref(B.t), _dptr(bb), bdeg,
+                                         nsteps, seed, C.byref(lo), C.byref(hi)),
+         "evsl_spectrum_bounds_gen")
+    return lo.value, hi.value
+
+
+def evsl_filtered_lanczos_gen(ctx, A, B, bbounds, bdeg, intv, pol, opts=None):
+    """Filtered non-restart Lanczos for (A, B): (lam, Y (B-orthonormal), res, stats)."""
+    bb = _f64(bbounds)
+    iv = _f64(intv)
+    out = EigsT()
+    opts = opts or lan_opts(method=EVSL_LAN_NR)
+    _chk(_lib().evsl_filtered_lanczos_gen(ctx.h, C.byref(A.t), C.byref(B.t), _dptr(bb), bdeg,
+                                          _dptr(iv), C.byref(pol.t), C.byref(opts), C.byref(out)),
+         "evsl_filtered_lanczos_gen", ok=(EVSL_OK, EVSL_ENOCONV))
+    return _take(ctx, out, A.n, A.val.device)

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libevsl_mi355.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "solver.hip", "subspace.hip", "host_poly.cpp", "host_eig.cpp"]
+SOURCES = ["kernels.hip", "solver.hip", "subspace.hip", "generalized.hip", "host_poly.cpp",
+           "host_eig.cpp"]
 ARCH = os.environ.get("EVSL_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every device compilation.

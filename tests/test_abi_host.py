@@ -120,3 +120,13 @@ def test_lanczos_count_and_slicer_match_oracle(sigma):
     assert np.array_equal(got, want)
     with pytest.raises(ev.EvslError):
         ev.evsl_lanczos_count(q, A.n, -1.0, 0.0, 1.0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_lspol_matches_oracle(kind):
+    for lo, hi, deg in ((0.1, 1.0, 30), (1.0, 9.0, 12)):
+        got = ev.evsl_lspol(kind, lo, hi, deg)
+        want = oracle.lspol(kind, lo, hi, deg)
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    with pytest.raises(ev.EvslError):
+        ev.evsl_lspol(kind, 0.0, 1.0, 5)

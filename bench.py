@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--rows", type=int, nargs="+", default=None,
                     help="--paper-table: rows to run (0-11, default all)")
     ap.add_argument("--methods", nargs="+", default=["nr"], choices=["nr", "tr"])
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP64 and FP32-filter solves of the same slices, eigenvalue by eigenvalue "
+                         "(default slices [0.50,0.60], [0.60,0.65], [0.60,0.625] of the grid)")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload: a Poisson stream of DOS and eigenpair requests")
     ap.add_argument("--requests", type=int, default=48)
@@ -436,6 +439,49 @@ def paper_table_main(args):
         "rows": out}), flush=True)
 
 
+def precision_main(args, ctx, ev, Ad, A):
+    """The precision form against FP64 on single slices whose Jackson degrees
+    span about 50-300: for each slice, both solves from the same bounds, KPM and
+    filter; eigenvalues matched in order, the FP32 form's error reported
+    against FP64 for every eigenvalue (max and median, relative to ||A||)."""
+    import copy
+    import torch
+
+    ivs = [(0.50, 0.60), (0.60, 0.65), (0.60, 0.625)]
+    out = []
+    for iv in ivs:
+        rec = {"interval": list(iv)}
+        lams = {}
+        for prec in ("f64", "f32"):
+            a = copy.copy(args)
+            a.interval, a.nslices, a.prec, a.slices, a.interval_count = list(iv), 1, prec, None, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = one_step(ctx, ev, Ad, a)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lams[prec] = r["lam"]
+            ps = r["per_slice"][0]
+            rec[prec] = {"nev": r["nev"], "s": dt, "deg": ps["deg"], "niter": ps["niter"],
+                         "npolish": ps["npolish"], "status": ps["status"],
+                         "max_residual": float(r["res"].max()) if r["nev"] else None}
+            print(f"[precision] {iv} {prec}: {r['nev']} pairs, degree {ps['deg']}, {dt:.1f} s",
+                  file=sys.stderr, flush=True)
+        l64, l32 = np.sort(lams["f64"]), np.sort(lams["f32"])
+        normA = max(abs(r["bounds"][0]), abs(r["bounds"][1]))
+        if len(l64) == len(l32) and len(l64):
+            err = np.abs(l32 - l64) / normA
+            rec["f32_vs_f64_eig_err"] = {"max": float(err.max()), "median": float(np.median(err))}
+        rec["speedup_f32"] = rec["f64"]["s"] / rec["f32"]["s"]
+        out.append(rec)
+    print(json.dumps({
+        "metric": "FP32-filter precision form vs FP64: eigenpairs and per-eigenvalue error",
+        "n_gpus": 1, "dtype": "f32-filter/f64 vs f64", "data": "synthetic",
+        "config": {"workload": (f"3-D 7-point Laplacian {args.grid}^3 + U[0,1) potential (seed 0), "
+                                f"single slices, tol {args.tol:g}")},
+        "slices": out}), flush=True)
+
+
 def serve_main(args):
     """Serving workload: a seeded Poisson stream of requests, each on its own
     matrix, admitted by device-memory footprint and run concurrently (one HIP
@@ -560,6 +606,9 @@ def main():
     ev.evsl_filter_apply(ctx, tiny, [pt], [0], xv, torch.empty_like(xv))
     torch.cuda.synchronize()
 
+    if args.precision_study:
+        precision_main(args, ctx, ev, Ad, A)
+        return
     for _ in range(args.warmup):
         one_step(ctx, ev, Ad, args)
     torch.cuda.synchronize()

@@ -1,0 +1,42 @@
+"""Host-side logic of bench.py on the CPU: the one-GPU rule, the counter
+summary's validity check, and the workload constants."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_counter_summary_matches_the_measured_kernel_source():
+    """The committed counters were taken on the current filter kernel: its
+    source hash matches, so the bench reports the traffic; any other text
+    would not match."""
+    import hashlib
+    src = bench.filter_kernel_source()
+    assert "k_cheb_blk_lds" in src and "template void cheb_blk<double>" in src
+    assert bench.measured_traffic() is not None
+    assert hashlib.sha256((src + " ").encode()).hexdigest() != \
+        hashlib.sha256(src.encode()).hexdigest()
+
+
+def test_paper_rows_are_the_printed_table():
+    assert len(bench.PAPER_ROWS) == 12
+    grids = {(r[0], r[1]) for r in bench.PAPER_ROWS}
+    assert grids == {(2, 343), (2, 729), (2, 1000), (3, 49), (3, 81), (3, 100)}
+    # nmv is about deg * niter (niter printed to the nearest ten) plus the Ritz
+    # checks, in every printed row
+    for r in bench.PAPER_ROWS:
+        deg, niter, nmv = r[5], r[6], r[7]
+        assert deg * niter <= nmv <= deg * (niter + 10) + 2 * r[4] + 100

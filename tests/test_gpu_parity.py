@@ -548,3 +548,34 @@ def test_lanczos_dos_matches_oracle(ctx, N, dim, pot):
             a = ev.evsl_lanczos_count(q, A.n, sigma, x0, x1)
             b = oracle.lanczos_count(oq, A.n, sigma, x0, x1)
             assert abs(a - b) <= 1e-8 * A.n, (x0, x1, sigma, a, b)
+
+
+def test_headline_workload_sampled_pairs_against_oracle(ctx):
+    """At the headline size and launch configuration (100^3 + potential, KPM
+    cut of [0.60, 0.70] into 10 slices, autotuned groups), the first slice's
+    pairs: every residual <= 1e-8, orthonormal vectors, and eight sampled pairs
+    re-checked with the oracle's FP64 product on the host."""
+    A = I.laplacian(100, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [0.60, 0.70, lo, hi]
+    mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 80, 20, seed=1, damping=ev.DAMP_JACKSON)
+    sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, 10, 2000)
+    iv = [sli[0], sli[1], lo, hi]
+    cnt = ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, sli[0], sli[1])
+    pol = _pol(iv)
+    g, _ = ev.evsl_autotune(ctx, Ad, 10)
+    lam, Y, res, st = ev.evsl_filtered_lanczos_batch(
+        ctx, Ad, [iv], [pol], [ev.lan_opts(tol=1e-8, seed=2, nev_est=int(cnt * 1.1) + 5)])[0]
+    ctx.set_group_width(0)
+    assert st["status"] == ev.EVSL_OK and len(lam) >= 0.7 * cnt
+    assert res.max() <= 1e-8
+    Yc = Y.contiguous()
+    G = (Yc.T.contiguous() @ Yc).cpu().numpy()
+    assert np.abs(G - np.eye(len(lam))).max() <= 1e-10
+    normA = max(abs(lo), abs(hi))
+    for j in np.linspace(0, len(lam) - 1, 8).astype(int):
+        y = Y[:, j].cpu().numpy()
+        r = np.linalg.norm(oracle.spmv(A, y) - lam[j] * y) / np.linalg.norm(y) / normA
+        assert r <= 1e-8, (j, r)
+        assert abs(y @ oracle.spmv(A, y) / (y @ y) - lam[j]) <= 1e-12 * normA

@@ -579,3 +579,28 @@ def test_headline_workload_sampled_pairs_against_oracle(ctx):
         r = np.linalg.norm(oracle.spmv(A, y) - lam[j] * y) / np.linalg.norm(y) / normA
         assert r <= 1e-8, (j, r)
         assert abs(y @ oracle.spmv(A, y) / (y @ y) - lam[j]) <= 1e-12 * normA
+
+
+def test_failed_device_allocation_reports_enomem_and_context_survives(ctx):
+    """A basis larger than the device (the lock capacity clamps to n, so about
+    n x n doubles: 328 GB for n = 202,500) makes the allocation fail: the solve
+    returns EVSL_ENOMEM, the context's memory ledger returns to where it was,
+    and the next solve on it succeeds."""
+    A = I.laplacian(450, 2, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.01, lo, hi]
+    p = _pol(intv)
+    cur0, _ = ctx.mem_stats()
+    with pytest.raises(ev.EvslError) as e:
+        ev.evsl_filtered_lanczos(ctx, Ad, intv, p, ev.lan_opts(nev_cap=10_000_000, nev_est=20))
+    assert e.value.code == ev.EVSL_ENOMEM
+    assert ctx.mem_stats()[0] == cur0
+    S = I.laplacian(24, 2, pot_seed=0)
+    Sd = ev.DeviceCsr.from_host(S)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Sd, 80, 3)
+    iv = [1.0, 1.5, lo, hi]
+    w = np.linalg.eigvalsh(S.to_dense())
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Sd, iv, _pol(iv), ev.lan_opts(nev_est=40))
+    assert st["status"] == ev.EVSL_OK and res.max() <= 1e-8
+    assert len(lam) == int(((w >= 1.0) & (w <= 1.5)).sum())

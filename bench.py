@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--kpm-degree", type=int, default=80)
     ap.add_argument("--kpm-vectors", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--m-factor", type=float, default=0.0,
+                    help="Lanczos dimension m = factor * nev_est + 30 (0: the library default)")
     ap.add_argument("--max-its", type=int, default=0,
                     help="cap on Lanczos steps per slice (profiling runs only; 0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -145,6 +147,7 @@ def one_step(ctx, ev, Ad, args):
                                    max_its=args.max_its))
         else:
             opts.append(ev.lan_opts(tol=args.tol, seed=2 + q, nev_est=nev_est,
+                                    m=int(args.m_factor * nev_est) + 30 if args.m_factor else 0,
                                     max_its=args.max_its,
                                     prec=ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64,
                                     tol_lo=args.tol_lo, polish_div=args.polish_div,

@@ -285,7 +285,7 @@ int evsl_spectrum_bounds_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_csr
                              const double bbounds[2], int bdeg, int nsteps, uint64_t seed,
                              double *lmin, double *lmax);
 /* Filtered non-restart Lanczos for (A, B) on one slice: Algorithm alg:LanAB
- * applied to (B rho(B^-1 A-hat), B), line 3 as eq:polyapp1 (per degree step one
+ * applied to (B rho(B^-1 A-hat), B), its product step as eq:polyapp1 (per degree step one
  * solve with B and one product with A), full reorthogonalisation, the settled
  * sum test of EVSL_LAN_NR; intv = {t_i, t_{i+1}, lambda_min, lambda_max} of the
  * pencil and pol from evsl_cheb_coeffs on it. opt as for the non-restart form

@@ -1096,7 +1096,7 @@ int or_lanczos_bounds_gen(int64_t n, const int32_t *rp, const int32_t *ci, const
   int dim = m;
   for (int i = 0; i < m; ++i) {
     double *wi = W + (size_t)i * n, *zi = Z + (size_t)i * n;
-    /* Algorithm alg:LanAB, lines 3-10 */
+    /* one step of Algorithm alg:LanAB */
     or_spmv(n, rp, ci, va, wi, z);
     if (i > 0)
       for (int64_t r = 0; r < n; ++r) z[r] -= beta * Z[(size_t)(i - 1) * n + r];

@@ -166,7 +166,7 @@ int or_lanczos_bounds_gen(int64_t n, const int32_t *rp, const int32_t *ci, const
                           const int32_t *rpb, const int32_t *cib, const double *vb, int nsteps,
                           uint64_t seed, double *lmin, double *lmax);
 /* Filtered non-restart Lanczos for (A, B): Algorithm alg:LanAB applied to the
- * pencil (B rho(B^(-1) A-hat), B) of eq:gen1, so that its line 3 is eq:polyapp1,
+ * pencil (B rho(B^(-1) A-hat), B) of eq:gen1, so that its product step is eq:polyapp1,
  * z = rho(A-hat B^(-1)) z_i - beta_i z_{i-1} with A-hat = (A - cB)/d; the
  * Chebyshev recurrence in A-hat B^(-1) needs one solve with B and one product
  * with A per degree step (exact solves here). Stopping as

@@ -1,8 +1,8 @@
 // Generalized problems A x = lambda B x with B symmetric positive definite
 // (Section 2.4). Algorithm alg:LanAB keeps two bases, W (B-orthonormal) and
 // Z = B W, so that inner products need no product with B; the filtered form
-// applies it to the pencil (B rho(B^(-1) A-hat), B) of eq:gen1, whose line 3
-// becomes eq:polyapp1: z = rho(A-hat B^(-1)) z_i - beta_i z_{i-1} with
+// applies it to the pencil (B rho(B^(-1) A-hat), B) of eq:gen1, whose product
+// step becomes eq:polyapp1: z = rho(A-hat B^(-1)) z_i - beta_i z_{i-1} with
 // A-hat = (A - cB)/d. The Chebyshev recurrence in M = A-hat B^(-1) needs, per
 // degree step, one solve with B and one product with A (Table tab:itercomp):
 // M v = (A u - c v)/d with u = B^(-1) v. Solves with B use the least-squares

@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--calib", type=int, default=4, help="requests served alone to calibrate")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-running", type=int, default=4)
+    ap.add_argument("--serve-log", default="",
+                    help="serving: append one JSON record per finished request to this file")
     return ap.parse_args()
 
 
@@ -521,10 +523,27 @@ def serve_main(args):
         f, _ = torch.cuda.mem_get_info()
         hw["used"] = max(hw["used"], free0 - f)
 
+    reqs_by_id = {}
+    jsonl = open(args.serve_log, "a") if args.serve_log else None
+
     def done(res):
         log(f"[serve] request {res.rid} {res.kind}: {res.status}, nev {res.nev}, "
             f"latency {res.latency:.2f} s")
+        if jsonl:
+            r = reqs_by_id.get(res.rid)
+            jsonl.write(json.dumps({
+                "rid": res.rid, "kind": res.kind, "status": res.status, "error": res.error,
+                "dim": r.dim if r else None, "n": r.n if r else None,
+                "target": r.target if r and r.kind == "eigs" else None,
+                "arrival_s": res.arrival, "start_s": res.start, "end_s": res.end,
+                "latency_s": res.latency, "nev": res.nev,
+                "max_residual": float(res.res.max()) if res.res is not None and len(res.res) else None,
+                "interval": list(res.interval) if res.interval else None,
+                "device_peak_bytes": res.lib_peak,
+                "footprint_bytes": S.footprint_bytes(r) if r else None}) + "\n")
+            jsonl.flush()
 
+    reqs_by_id.update({r.rid: r for r in reqs})
     led = S.Ledger(budget, args.max_running)
     srv = S.Server(led, ex, on_tick=tick, on_result=done)
     t0 = time.perf_counter()

@@ -89,7 +89,7 @@ typedef struct {
 /* Options of the filtered Lanczos (Algorithm alg:FiltLanTR). Zero fields take
  * the documented defaults. */
 typedef struct {
-  int m;          /* Krylov dimension per cycle; 0: max(2 nev_est + 30, 60);
+  int m;          /* Krylov dimension per cycle; 0: max(3 nev_est + 30, 60);
                      EVSL_LAN_NR: total step cap; 0: max(5 nev_est + 200, 400) */
   int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) (EVSL_LAN_NR: m) */
   int ncycle;     /* early-restart test period; 0: 30 */
@@ -112,7 +112,7 @@ typedef struct {
  * the previous test and the run ends once it has settled (relative change
  * < 1e-10) or after m steps (then EVSL_ENOCONV). The Ritz vectors of all Ritz
  * values >= bar are then checked against A, in chunks of
- * max(2 nev_est + 30, 60) columns; those inside the slice with residual <= tol
+ * max(3 nev_est + 30, 60) columns; those inside the slice with residual <= tol
  * are returned (at most nev_cap). Device memory: (nev_cap + m + 1) basis
  * columns plus two chunks. */
 /* Precision form (prec = EVSL_F32): the filter recurrence runs in FP32 values,

@@ -236,7 +236,7 @@ def filtered_lanczos(A, intv, pol, m=None, max_its=None, ncycle=30, tol=1e-10, s
     if nev_est is None:
         nev_est = 50
     if m is None:
-        m = max(2 * int(nev_est) + 30, 60)
+        m = max(3 * int(nev_est) + 30, 60)
     if max_its is None:
         max_its = max(20 * m, 2000)
     if nev_cap is None:

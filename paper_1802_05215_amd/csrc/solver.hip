@@ -157,7 +157,7 @@ struct Slice {
     if (opt && opt->method != EVSL_LAN_TR && opt->method != EVSL_LAN_NR) fail(EVSL_EINVAL);
     nr = opt && opt->method == EVSL_LAN_NR;
     if (nr && opt->prec != EVSL_F64) fail(EVSL_ENOTIMPL);
-    const int m_tr = std::max(2 * nev_est + 30, 60);
+    const int m_tr = std::max(3 * nev_est + 30, 60);
     m = (opt && opt->m > 0) ? opt->m : (nr ? std::max(5 * nev_est + 200, 400) : m_tr);
     if (m > n - 1) m = n - 1;
     if (m < 2) fail(EVSL_EINVAL);

@@ -102,7 +102,7 @@ def poisson_stream(seed: int, count: int, rate: float, n_min: float = 1e4, n_max
 
 # ---------------------------------------------------------------- footprint
 # The sizes below follow the library's allocation rules: Krylov dimension
-# m = max(2 nev_est + 30, 60), lock capacity max(2 nev_est + 40, 100), a
+# m = max(3 nev_est + 30, 60), lock capacity max(2 nev_est + 40, 100), a
 # basis of (capacity + m + 1) columns with leading dimension n rounded up to
 # 64, workspace slots that grow to the largest use and live until the
 # context is destroyed, and result vectors (at most the lock capacity per
@@ -124,7 +124,7 @@ def _blk_partials(n: int, nc: int) -> int:
 
 
 def _lan_sizes(nev_est: int, n: int):
-    m = min(max(2 * nev_est + 30, 60), n - 1)
+    m = min(max(3 * nev_est + 30, 60), n - 1)
     cap = min(max(2 * nev_est + 40, 100), n)
     return m, cap
 

@@ -265,4 +265,73 @@ void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const do
   }
 }
 
+// All eigenvalues (ascending, in w) of the symmetric m x m A (overwritten)
+// and the eigenvectors of those >= thr only: Householder reduction with the
+// reflectors kept, QR for the eigenvalues of the tridiagonal, inverse
+// iteration for the selected eigenvectors of the tridiagonal, and the
+// reflectors applied to those vectors. O(m^3) for the reduction but only
+// O(m^2 nsel) for the vectors. Vsel: m x nsel column-major, in the order of
+// w[m - nsel .. m - 1]; returns nsel.
+int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel) {
+  if (m <= 0) return -1;
+  auto a = [&](int i, int j) -> double & { return A[i + (size_t)j * m]; };
+  std::vector<double> R((size_t)m * m, 0.0), betas(m, 0.0);  // reflector k in column k
+  std::vector<double> v(m), p(m), q(m);
+  for (int k = 0; k + 2 < m; ++k) {
+    const int len = m - k - 1;
+    double sig = 0.0;
+    for (int i = 0; i < len; ++i) sig += a(k + 1 + i, k) * a(k + 1 + i, k);
+    if (sig == 0.0) continue;
+    const double x0 = a(k + 1, k);
+    const double alpha = x0 >= 0 ? -std::sqrt(sig) : std::sqrt(sig);
+    for (int i = 0; i < len; ++i) v[i] = a(k + 1 + i, k);
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (int i = 0; i < len; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    for (int i = 0; i < len; ++i) {
+      double t = 0.0;
+      for (int j = 0; j < len; ++j) t += a(k + 1 + i, k + 1 + j) * v[j];
+      p[i] = beta * t;
+    }
+    double pv = 0.0;
+    for (int i = 0; i < len; ++i) pv += p[i] * v[i];
+    const double kk = 0.5 * beta * pv;
+    for (int i = 0; i < len; ++i) q[i] = p[i] - kk * v[i];
+    for (int j = 0; j < len; ++j)
+      for (int i = 0; i < len; ++i) a(k + 1 + i, k + 1 + j) -= v[i] * q[j] + q[i] * v[j];
+    a(k + 1, k) = alpha;
+    a(k, k + 1) = alpha;
+    for (int i = 1; i < len; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+    for (int i = 0; i < len; ++i) R[(k + 1 + i) + (size_t)k * m] = v[i];
+    betas[k] = beta;
+  }
+  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+  for (int i = 0; i < m; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < m; ++i) e[i] = a(i + 1, i);
+  {
+    std::vector<double> d2(d), e2(e);
+    tridiag_eig(m, d2.data(), e2.data(), w, nullptr);
+  }
+  int first = m;
+  while (first > 0 && w[first - 1] >= thr) --first;
+  const int nsel = m - first;
+  if (nsel == 0) return 0;
+  tridiag_eigvecs(m, d.data(), e.data(), nsel, w + first, Vsel);
+  // V = H_0 H_1 ... H_{m-3} Z, applied from the last reflector to the first
+  for (int k = m - 3; k >= 0; --k) {
+    if (betas[k] == 0.0) continue;
+    const double *vk = R.data() + (size_t)k * m;
+    for (int c = 0; c < nsel; ++c) {
+      double *z = Vsel + (size_t)c * m;
+      double t = 0.0;
+      for (int i = k + 1; i < m; ++i) t += vk[i] * z[i];
+      t *= betas[k];
+      for (int i = k + 1; i < m; ++i) z[i] -= t * vk[i];
+    }
+  }
+  return nsel;
+}
+
 }  // namespace evh

@@ -40,6 +40,9 @@ int sym_eig(int m, double *A, double *w, double *V);
 // off-diagonal e (both overwritten); V as in sym_eig (identity or a prior
 // transformation, m x m) or null. O(m^2) without vectors.
 int tridiag_eig(int m, double *d, double *e, double *w, double *V);
+// All eigenvalues of the symmetric A (overwritten), ascending, and the
+// eigenvectors of those >= thr (Vsel, m x nsel, same order); returns nsel.
+int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel);
 // Eigenvectors of the tridiagonal (d, e) for nsel eigenvalues lam (ascending)
 // by inverse iteration; Z is m x nsel column-major.
 void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const double *lam,

@@ -486,13 +486,16 @@ struct Slice {
     Uc = (double *)ws(ctx, 40, sizeof(double) * ld * m);
     AUc = (double *)ws(ctx, 41, sizeof(double) * ld * m);
     const double lock_tol = prec == EVSL_F32 ? std::max(tol, tol_lo) : tol;
-    std::vector<double> T = build_T(dim), w(dim), Y((size_t)dim * dim);
-    evh::sym_eig(dim, T.data(), w.data(), Y.data());
+    // all Ritz values, and the eigenvectors of T for the candidates only
+    // (Ritz values >= bar); Ysel column j - first belongs to Ritz value j
+    std::vector<double> T = build_T(dim), w(dim), Ysel((size_t)dim * dim);
+    const int first = dim - evh::sym_eig_sel(dim, T.data(), w.data(), bar, Ysel.data());
     check_filtered(w);
+    auto Ycol = [&](int j) { return Ysel.begin() + (size_t)(j - first) * dim; };
     const double beta_last = next_ok ? beta[dim - 1] : 0.0;
     // candidates: Ritz values >= bar, largest first
     std::vector<int> cand;
-    for (int j = dim - 1; j >= 0 && w[j] >= bar; --j) cand.push_back(j);
+    for (int j = dim - 1; j >= first; --j) cand.push_back(j);
     const int lc = (int)cand.size();
     int naccept = 0;
     std::vector<int> lock_sel, tr_sel;
@@ -502,8 +505,7 @@ struct Slice {
     if (lc > 0) {
       std::vector<double> Yh((size_t)dim * lc);
       for (int t = 0; t < lc; ++t)
-        std::copy(Y.begin() + (size_t)cand[t] * dim, Y.begin() + (size_t)cand[t] * dim + dim,
-                  Yh.begin() + (size_t)t * dim);
+        std::copy(Ycol(cand[t]), Ycol(cand[t]) + dim, Yh.begin() + (size_t)t * dim);
       HC(ctx, hipMemcpyAsync(Yc, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice,
                              st()));
       // U_c = Q_dim Y_c ; A U_c ; Rayleigh quotients and residuals
@@ -558,7 +560,7 @@ struct Slice {
         HC(ctx, hipMemcpyAsync(col(nlock + (int)q), Uc + (int64_t)t * ld, sizeof(double) * n,
                                hipMemcpyDeviceToDevice, st()));
         th_tr.push_back(w[cand[t]]);
-        s_tr.push_back(beta_last * Y[(dim - 1) + (size_t)cand[t] * dim]);
+        s_tr.push_back(beta_last * Ycol(cand[t])[dim - 1]);
       }
     }
     if (naccept == 0) {

@@ -483,7 +483,9 @@ int or_lanczos_bounds(int64_t n, const int32_t *rp, const int32_t *ci, const dou
  *  - the special TR step couples q_{l+1} to the l thick-restart Ritz vectors
  *    through s_j = beta_{m+1} y_{m,j} (arrowhead T, as in Wu and Simon 2000);
  *  - full reorthogonalisation runs against the locked vectors and the basis;
- *  - the early-restart sums start afresh in each cycle;
+ *  - the early-restart sums carry over from one cycle to the next (the
+ *    algorithm sets t_old = t_new at each test and initialises neither per
+ *    cycle);
  *  - a restart that accepts no candidate (none with a Rayleigh quotient in the
  *    slice) starts the next cycle from a fresh random vector orthogonalised
  *    against the locked set (the extra restart), and two such restarts in a
@@ -535,9 +537,11 @@ int or_filtered_lanczos(int64_t n, const int32_t *rp, const int32_t *ci, const d
   /* q_1: seeded random unit vector */
   fresh_vector(n, opt->seed, nrand++, Q, NULL, 0, NULL, 0, h, &nz);
 
+  /* the early-restart sums are initialised once, before the outer loop, and
+   * carry over from one cycle to the next */
+  double t_old = NAN, t_new = NAN;
   while (its <= opt->max_its) {
     /* Lanczos steps i = l+1..m (0-based column i = l..m-1 produces column i+1) */
-    double t_old = NAN, t_new = NAN;
     int dim = m, next_ok = 1;
     for (int i = l; i < m; ++i) {
       its++;

@@ -601,8 +601,7 @@ struct Slice {
     }
     std::fill(alpha.begin(), alpha.end(), 0.0);
     std::fill(beta.begin(), beta.end(), 0.0);
-    i = l;
-    t_old = t_new = NAN;
+    i = l;  // the early-restart sums carry over into the next cycle
     if (nlock + m + 1 > cap_cols) {
       status = EVSL_ENOMEM;
       done = true;

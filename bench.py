@@ -84,6 +84,10 @@ def parse():
     ap.add_argument("--precision-study", action="store_true",
                     help="FP64 and FP32-filter solves of the same slices, eigenvalue by eigenvalue "
                          "(default slices [0.50,0.60], [0.60,0.65], [0.60,0.625] of the grid)")
+    ap.add_argument("--small", action="store_true",
+                    help="the 40x40 plain case: whole-path latency over repeated solves, "
+                         "with and without HIP graphs")
+    ap.add_argument("--repeats", type=int, default=50)
     ap.add_argument("--serve", action="store_true",
                     help="serving workload: a Poisson stream of DOS and eigenpair requests")
     ap.add_argument("--requests", type=int, default=48)
@@ -444,6 +448,104 @@ def paper_table_main(args):
         "rows": out}), flush=True)
 
 
+def small_main(args):
+    """The small plain case: 2-D 40x40 Laplacian without potential, [1.0, 1.6]
+    (91 eigenvalues, 44 of them exact double pairs). Each repeat runs the whole
+    path (Lanczos bounds, KPM degree 40 with 10 vectors, slicing, Jackson
+    filters, thick-restart solve at tol 1e-10) from a device-resident matrix;
+    p50/p99 latency over the repeats, time per filter degree step and per
+    Lanczos step, for one and two slices, with the filter replayed from HIP
+    graphs and launched kernel by kernel. Every repeat is checked against the
+    closed form 4 - 2 cos(i pi/41) - 2 cos(j pi/41)."""
+    import torch
+
+    import evsl_inputs as I
+    import paper_1802_05215_amd as ev
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    N, intv0, tol = 40, (1.0, 1.6), 1e-10
+    A = I.laplacian(N, 2)
+    Ad = ev.DeviceCsr.from_host(A, device="cuda:0")
+    c = 2.0 - 2.0 * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    ex = np.sort((c[:, None] + c[None, :]).ravel())
+    want = ex[(ex >= intv0[0]) & (ex <= intv0[1])]
+    ctx = ev.Ctx()
+
+    def solve(ns):
+        t0 = time.perf_counter()
+        lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+        intv = [intv0[0], intv0[1], lo, hi]
+        mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 40, 10, seed=1, damping=ev.DAMP_JACKSON)
+        sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, ns, 2000) if ns > 1 \
+            else np.array(intv0)
+        ivs, pols, opts = [], [], []
+        for q in range(ns):
+            iv = [sli[q], sli[q + 1], lo, hi]
+            cnt = ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, sli[q], sli[q + 1])
+            ivs.append(iv)
+            pols.append(ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON, tau=0.8, tau_ext=0.4))
+            opts.append(ev.lan_opts(tol=tol, seed=2 + q, nev_est=max(int(cnt * 1.1) + 5, 10)))
+        t1 = time.perf_counter()
+        if ns == 1:
+            outs = [ev.evsl_filtered_lanczos(ctx, Ad, ivs[0], pols[0], opts[0])]
+        else:
+            outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lams = []
+        for q, (lam, Y, res, st) in enumerate(outs):
+            keep = (lam >= ivs[q][0]) & ((lam < ivs[q][1]) | (q == ns - 1)) & (res <= tol)
+            lams.append(lam[keep])
+        lam = np.sort(np.concatenate(lams))
+        err = float(np.abs(lam - want).max() / np.abs(want).max()) if len(lam) == len(want) \
+            else float("inf")
+        return dict(t=t2 - t0, t_solve=t2 - t1, nev=len(lam), err=err,
+                    niter=sum(o[3]["niter"] for o in outs), degs=[p.deg for p in pols])
+
+    rows = []
+    for graphs in (True, False):
+        ctx.set_graphs(graphs)
+        for ns in (1, 2):
+            for _ in range(3):
+                solve(ns)
+            torch.cuda.synchronize()
+            ctx.reset_stats()
+            recs = [solve(ns) for _ in range(args.repeats)]
+            fs = ctx.filter_stats()
+            t = np.array([r["t"] for r in recs])
+            ts = np.array([r["t_solve"] for r in recs])
+            steps = sum(r["niter"] for r in recs)
+            row = {"graphs": graphs, "slices": ns, "degrees": recs[0]["degs"],
+                   "nev": [r["nev"] for r in recs][0], "all_correct":
+                   all(r["nev"] == len(want) and r["err"] <= 1e-10 for r in recs),
+                   "max_rel_err": max(r["err"] for r in recs),
+                   "p50_ms": float(np.percentile(t, 50)) * 1e3,
+                   "p99_ms": float(np.percentile(t, 99)) * 1e3,
+                   "solve_p50_ms": float(np.percentile(ts, 50)) * 1e3,
+                   "lanczos_steps": recs[0]["niter"],
+                   "us_per_lanczos_step": float(ts.sum()) / steps * 1e6,
+                   "us_per_filter_step": fs["seconds"] / max(fs["launches"], 1) * 1e6,
+                   "filter_steps_per_lanczos_step": fs["launches"] / max(steps, 1)}
+            rows.append(row)
+            log(f"[small] graphs {graphs} slices {ns}: p50 {row['p50_ms']:.1f} ms "
+                f"p99 {row['p99_ms']:.1f} ms, {row['us_per_lanczos_step']:.1f} us per Lanczos "
+                f"step, {row['us_per_filter_step']:.2f} us per filter step, nev {row['nev']}, "
+                f"correct {row['all_correct']}")
+    ctx.set_graphs(True)
+    best = min(r["p50_ms"] for r in rows)
+    print(json.dumps({
+        "metric": "whole-path latency, 40x40 plain case (p50 over repeats)",
+        "value": best, "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2-D 5-point Laplacian 40x40 (n 1600), no potential, "
+                               "[1.0, 1.6] (91 eigenvalues), KPM degree 40 with 10 vectors, "
+                               f"Jackson filters, thick-restart Lanczos, tol {tol:g}",
+                   "repeats": args.repeats},
+        "rows": rows}), flush=True)
+
+
 def precision_main(args, ctx, ev, Ad, A):
     """The precision form against FP64 on single slices whose Jackson degrees
     span about 50-300: for each slice, both solves from the same bounds, KPM and
@@ -592,7 +694,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.serve or args.filter_only or args.paper_table:
+    if args.serve or args.filter_only or args.paper_table or args.small:
         import torch
         import paper_1802_05215_amd as ev
         if not torch.cuda.is_available():
@@ -604,6 +706,8 @@ def main():
             serve_main(args)
         elif args.paper_table:
             paper_table_main(args)
+        elif args.small:
+            small_main(args)
         else:
             filter_only_main(args)
         return

@@ -135,6 +135,8 @@ typedef struct {
   int nrestart;
   int npolish;    /* FP64 polish rounds (precision form) */
   int status;     /* EVSL_OK or EVSL_ENOCONV */
+  int north2;     /* Lanczos steps whose reorthogonalisation made a second
+                     Gram-Schmidt pass (DGKS test, Section 2.3) */
   double t_mv;    /* seconds in filter products */
   double t_orth;  /* seconds in reorthogonalisation */
   double t_ritz;  /* seconds in Rayleigh-Ritz, locking and restarts */

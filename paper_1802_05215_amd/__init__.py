@@ -70,7 +70,8 @@ class SiOptsT(C.Structure):
 class EigsT(C.Structure):
     _fields_ = [("nev", C.c_int), ("lam", C.POINTER(C.c_double)), ("res", C.POINTER(C.c_double)),
                 ("Y", C.c_void_p), ("niter", C.c_int), ("nmv", C.c_int), ("nrestart", C.c_int),
-                ("npolish", C.c_int), ("status", C.c_int), ("t_mv", C.c_double), ("t_orth", C.c_double),
+                ("npolish", C.c_int), ("status", C.c_int), ("north2", C.c_int),
+                ("t_mv", C.c_double), ("t_orth", C.c_double),
                 ("t_ritz", C.c_double), ("t_tot", C.c_double)]
 
 
@@ -405,7 +406,7 @@ def _take(ctx, out, n, device):
              "evsl_eigs_get_vectors")
         torch.cuda.current_stream().synchronize()
     stats = dict(nev=k, niter=out.niter, nmv=out.nmv, nrestart=out.nrestart, npolish=out.npolish,
-                 status=out.status,
+                 north2=out.north2, status=out.status,
                  t_mv=out.t_mv, t_orth=out.t_orth, t_ritz=out.t_ritz, t_tot=out.t_tot)
     _lib().evsl_eigs_free(ctx.h, C.byref(out))
     return lam, Yt.T, res, stats

@@ -188,6 +188,19 @@ inline hipStream_t capture_stream(evsl_ctx_t ctx) {
   return ctx->cap_stream;
 }
 
+// Ends a capture left open by an error, so the stream stays usable.
+struct CaptureGuard {
+  hipStream_t s;
+  bool open = false;
+  ~CaptureGuard() {
+    if (open) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  }
+};
+
 inline evk::Csr to_csr(const evsl_csr_t *A) {
   evk::Csr c;
   c.n = (int)A->n;

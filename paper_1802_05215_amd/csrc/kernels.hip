@@ -569,8 +569,13 @@ template void scatter_cols<float>(hipStream_t, int, int, const float *, int64_t,
 // ---------------------------------------------------------------- reductions over columns
 // out[c] = scale * sum_w partial[c * nw + w]; one workgroup per column.
 __global__ __launch_bounds__(TPB) void k_reduce_partials(int nw, const double *partial,
-                                                         double scale, double *out) {
+                                                         double scale, double *out,
+                                                         const int *gate) {
   __shared__ double red[4];
+  if (gate && gate[0] == 0) {
+    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
+    return;
+  }
   const double *p = partial + (int64_t)blockIdx.x * nw;
   double acc = 0.0;
   for (int w = threadIdx.x; w < nw; w += TPB) acc += p[w];
@@ -579,9 +584,10 @@ __global__ __launch_bounds__(TPB) void k_reduce_partials(int nw, const double *p
 }
 
 void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
-                     double *out) {
+                     double *out, const int *gate) {
   if (ncol <= 0) return;
-  hipLaunchKernelGGL(k_reduce_partials, dim3(ncol), dim3(TPB), 0, s, nw, partial, scale, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(ncol), dim3(TPB), 0, s, nw, partial, scale, out,
+                     gate);
 }
 
 // h = B^T z, partial sums per 64*RPL-row chunk; wave w of the workgroup takes
@@ -596,7 +602,8 @@ static constexpr int GEMV_COLS = 64;
 
 __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const double *__restrict__ B,
                                                         int64_t ld, const double *__restrict__ z,
-                                                        double *partial) {
+                                                        double *partial, const int *gate) {
+  if (gate && gate[0] == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.x * GEMV_ROWS;
   double zr[GEMV_RPL];
@@ -623,19 +630,24 @@ __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const dou
 int gemv_partials(int n, int nb) { return ((n + GEMV_ROWS - 1) / GEMV_ROWS) * std::max(nb, 1); }
 
 void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *z,
-            double *partial, double *h) {
+            double *partial, double *h, const int *gate) {
   if (nb <= 0 || n <= 0) return;
   const int nwg = (n + GEMV_ROWS - 1) / GEMV_ROWS;
   hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg, (nb + GEMV_COLS - 1) / GEMV_COLS), dim3(TPB), 0, s,
-                     n, nb, B, ld, z, partial);
-  reduce_partials(s, nwg, nb, partial, 1.0, h);
+                     n, nb, B, ld, z, partial, gate);
+  reduce_partials(s, nwg, nb, partial, 1.0, h, gate);
 }
 
-// z -= B h, one row per thread, h staged through LDS in chunks.
+// z -= B h, one row per thread, h staged through LDS in chunks. With NRM the
+// workgroup also writes the sum of squares of its rows of the updated z.
+template <bool NRM>
 __global__ __launch_bounds__(TPB) void k_gemv_n_sub(int n, int nb, const double *__restrict__ B,
                                                     int64_t ld, const double *__restrict__ h,
-                                                    double *z) {
+                                                    double *z, const int *gate,
+                                                    double *nrm_partial) {
   __shared__ double sh[1024];
+  __shared__ double red[4];
+  if (gate && gate[0] == 0) return;
   const int r = blockIdx.x * TPB + threadIdx.x;
   double acc = 0.0;
   for (int j0 = 0; j0 < nb; j0 += 1024) {
@@ -649,14 +661,54 @@ __global__ __launch_bounds__(TPB) void k_gemv_n_sub(int n, int nb, const double 
       for (int j = 0; j < cnt; ++j) acc += b[(int64_t)j * ld] * sh[j];
     }
   }
-  if (r < n) z[r] -= acc;
+  double zn = 0.0;
+  if (r < n) {
+    zn = z[r] - acc;
+    z[r] = zn;
+  }
+  if (NRM) {
+    const double b = block_sum(zn * zn, red);
+    if (threadIdx.x == 0) nrm_partial[blockIdx.x] = b;
+  }
 }
 
 void gemv_n_sub(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
-                double *z) {
+                double *z, const int *gate) {
   if (nb <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(k_gemv_n_sub, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, nb, B, ld, h,
-                     z);
+  hipLaunchKernelGGL(k_gemv_n_sub<false>, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, nb, B,
+                     ld, h, z, gate, nullptr);
+}
+
+int nrm_partials(int n) { return std::max((n + TPB - 1) / TPB, 1); }
+
+void gemv_n_sub_nrm(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
+                    double *z, double *nrm_partial) {
+  if (nb <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_gemv_n_sub<true>, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, nb, B, ld,
+                     h, z, nullptr, nrm_partial);
+}
+
+// DGKS test of a classical Gram-Schmidt pass (Section 2.3): with the
+// orthonormal basis, the norm of z before the pass, taken without the
+// components the three-term recurrence accounts for, is sqrt(after^2 + S),
+// S = sum of h[j]^2 over the other columns [lo, hi). A second pass is made
+// when after < before / sqrt(2), i.e. when after^2 < S.
+__global__ __launch_bounds__(TPB) void k_dgks_gate(int nw, const double *nrm_partial,
+                                                   const double *h, int lo, int hi, int *gate) {
+  __shared__ double red[4];
+  double a = 0.0, sq = 0.0;
+  for (int w = threadIdx.x; w < nw; w += TPB) a += nrm_partial[w];
+  for (int j = lo + threadIdx.x; j < hi; j += TPB) sq += h[j] * h[j];
+  const double after2 = block_sum(a, red);
+  __syncthreads();
+  const double other = block_sum(sq, red);
+  if (threadIdx.x == 0) gate[0] = after2 < other ? 1 : 0;
+}
+
+void dgks_gate(hipStream_t s, int n, const double *nrm_partial, const double *h, int lo, int hi,
+               int *gate) {
+  hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(TPB), 0, s, nrm_partials(n), nrm_partial, h, lo,
+                     std::max(hi, lo), gate);
 }
 
 // Column dots and residual norms: 2048-row chunks, grid.y over columns.

@@ -57,11 +57,21 @@ void gemm_tn(hipStream_t s, int n, int p, int q, const double *X, int64_t ldx, c
 // h[j] = B[:, j] . z  for j < nb (B column-major, leading dim ld); uses
 // `partial` (gemv_partials(n, nb) doubles). Deterministic order.
 int gemv_partials(int n, int nb);
+// With `gate` set, the launches do nothing and h = 0 when gate[0] == 0.
 void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *z,
-            double *partial, double *h);
-// z -= B h
+            double *partial, double *h, const int *gate = nullptr);
+// z -= B h (nothing when gate is set and gate[0] == 0)
 void gemv_n_sub(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
-                double *z);
+                double *z, const int *gate = nullptr);
+// z -= B h, and per-workgroup sums of squares of the new z into nrm_partial
+// (nrm_partials(n) doubles)
+int nrm_partials(int n);
+void gemv_n_sub_nrm(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
+                    double *z, double *nrm_partial);
+// gate[0] = 1 when a second Gram-Schmidt pass is due: ||z||^2 (from the
+// partials of gemv_n_sub_nrm) < sum of h[j]^2 over j in [lo, hi)
+void dgks_gate(hipStream_t s, int n, const double *nrm_partial, const double *h, int lo, int hi,
+               int *gate);
 // out[c] = X[:, c] . Y[:, c] for c < ncol (column-major, strides ldx, ldy).
 int dot_partials(int n, int ncol);
 void col_dots(hipStream_t s, int n, int ncol, const double *X, int64_t ldx, const double *Y,
@@ -83,7 +93,7 @@ void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double 
 // Final fixed-order reduction of nw partial sums per column:
 // out[c] = scale * sum_w partial[c * nw + w].
 void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, double scale,
-                     double *out);
+                     double *out, const int *gate = nullptr);
 // y += a x over len doubles.
 void axpy(hipStream_t s, int64_t len, double a, const double *x, double *y);
 // Plain copy of `bytes` (a multiple of 16) from x to y: the bandwidth reference.

@@ -27,14 +27,16 @@ namespace {
 // --------------------------------------------------------------------------
 // Orthogonalisation helpers on a column-major basis B (n x *, leading dim ld).
 struct OrthWork {
-  double *partial;  // gemv_partials(n, ncap) doubles
-  double *h1, *h2;  // ncap
-  double *nrm2;     // 1 + ncol
-  double *scal;     // 4 per slot
+  double *partial = nullptr;  // gemv_partials(n, ncap) doubles
+  double *h1 = nullptr, *h2 = nullptr;  // ncap
+  double *nrm2 = nullptr;     // 1 + ncol
+  double *scal = nullptr;     // 4 per slot
+  double *npart = nullptr;    // nrm_partials(n): squared norm after the first pass
+  int *gate = nullptr;        // 1: the second pass is made
 };
 
 // z <- z - B(B^T z), twice (classical Gram-Schmidt, second pass always made);
-// stores h1 + h2 into h1.
+// the coefficients of the passes are left in h1 and h2.
 void cgs2(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, OrthWork &w) {
   if (nb <= 0) return;
   evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h1);
@@ -43,11 +45,29 @@ void cgs2(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, 
   evk::gemv_n_sub(s, n, nb, B, ld, w.h2, z);
 }
 
+// Full reorthogonalisation of a Lanczos step (Section 2.3): one classical
+// Gram-Schmidt pass against the first nb columns of B, and a second one only
+// when the DGKS test asks for it. The first pass also removes the components
+// the three-term recurrence accounts for (alpha along q_i, the coupling to the
+// previous vector or to the thick-restart block), so the test counts only the
+// coefficients of the columns [lo, hi) outside them. h2 = 0 when the second
+// pass is skipped; the decision stays on the device.
+void cgs_dgks(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, OrthWork &w,
+              int lo, int hi) {
+  if (nb <= 0) return;
+  evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h1);
+  evk::gemv_n_sub_nrm(s, n, nb, B, ld, w.h1, z, w.npart);
+  evk::dgks_gate(s, n, w.npart, w.h1, lo, hi, w.gate);
+  evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h2, w.gate);
+  evk::gemv_n_sub(s, n, nb, B, ld, w.h2, z, w.gate);
+}
+
 __global__ void k_step_scalars(const double *h1, const double *h2, int idx, const double *nrm2,
-                               double *out) {
+                               double *out, const int *gate) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     out[0] = idx >= 0 ? h1[idx] + h2[idx] : 0.0;
     out[1] = sqrt(nrm2[0]);
+    if (gate) out[2] = (double)gate[0];
   }
 }
 
@@ -94,6 +114,12 @@ struct Slice {
   int64_t ld = 0;
   int cap_cols = 0;
   double *z = nullptr, *w0 = nullptr, *w1 = nullptr;  // filter output and recurrence work
+  // graph form of the single-vector filter: the deg launches read a fixed
+  // input (qin, or q32 in FP32) so one captured graph serves every step
+  double *qin = nullptr;
+  hipGraph_t fg = nullptr;
+  hipGraphExec_t fgx = nullptr;
+  int fg_var = -1;
   double *Uc = nullptr, *AUc = nullptr, *Yc = nullptr;
   OrthWork ow{};
   double *hostsc = nullptr;  // pinned: 2 scalars of the last step
@@ -102,6 +128,7 @@ struct Slice {
   std::vector<double> th_tr, s_tr;  // thick-restart diagonal and arrow
   std::vector<double> lam, res;     // locked pairs in lock order
   int nlock = 0, l = 0, i = 0, its = 0, nmv = 0, nrand = 0, nocand = 0, nrestart = 0;
+  int npass2 = 0;  // Lanczos steps whose reorthogonalisation took a second pass
   double t_old = NAN, t_new = NAN;
   bool done = false;
   int status = EVSL_OK;
@@ -114,10 +141,14 @@ struct Slice {
   Slice &operator=(const Slice &) = delete;
   ~Slice() { release(); }
   void release() {
-    void *bufs[] = {coef_dev, B, z, w0, w1, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2, ow.scal,
-                    own32, q32, w0f, w1f, zf};
+    if (fgx) (void)hipGraphExecDestroy(fgx);
+    if (fg) (void)hipGraphDestroy(fg);
+    fgx = nullptr;
+    fg = nullptr;
+    void *bufs[] = {coef_dev, B, z, w0, w1, qin, Yc, ow.partial, ow.h1, ow.h2, ow.nrm2, ow.scal,
+                    ow.npart, ow.gate, own32, q32, w0f, w1f, zf};
     for (void *p : bufs) dfree(ctx, p);
-    coef_dev = B = z = w0 = w1 = Uc = AUc = Yc = nullptr;
+    coef_dev = B = z = w0 = w1 = qin = Uc = AUc = Yc = nullptr;
     own32 = q32 = w0f = w1f = zf = nullptr;
     ow = OrthWork{};
     if (hostsc) (void)hipHostFree(hostsc);
@@ -187,6 +218,7 @@ struct Slice {
     z = (double *)dalloc(ctx, sizeof(double) * ld);
     w0 = (double *)dalloc(ctx, sizeof(double) * ld);
     w1 = (double *)dalloc(ctx, sizeof(double) * ld);
+    if (prec == EVSL_F64) qin = (double *)dalloc(ctx, sizeof(double) * ld);
     // Ritz scratch (m columns) is shared by all slices of a context: restarts
     // run one slice at a time on the context stream
     (void)ws(ctx, 40, sizeof(double) * ld * cmax);
@@ -215,6 +247,8 @@ struct Slice {
     ow.h2 = (double *)dalloc(ctx, sizeof(double) * ncap);
     ow.nrm2 = (double *)dalloc(ctx, sizeof(double) * (3 * m + 8));
     ow.scal = (double *)dalloc(ctx, sizeof(double) * 8);
+    ow.npart = (double *)dalloc(ctx, sizeof(double) * evk::nrm_partials(n));
+    ow.gate = (int *)dalloc(ctx, sizeof(int) * 4);
     coef_dev = (double *)dalloc(ctx, sizeof(double) * (deg + 1));
     HC(ctx, hipMemcpyAsync(coef_dev, coef.data(), sizeof(double) * (deg + 1),
                            hipMemcpyHostToDevice, st()));
@@ -277,34 +311,73 @@ struct Slice {
   void filter_vector_async() {
     const int var = pick_variant(ctx);
     const double *q = current();
-    if (prec == EVSL_F32) {
-      // FP32 recurrence: values, vectors and accumulation in float
-      const evk::Csr A32 = csr32();
-      evk::to_f32(st(), n, q, q32);
-      evk::cheb_vec<float>(st(), A32, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q32, nullptr, w0f,
-                           zf, ld, 1, coef_dev, deg + 1, 1);
-      const float *wprev = q32;
-      float *wcur = w0f;
-      for (int j = 1; j < deg; ++j) {
-        float *dst = (wprev == q32) ? w1f : const_cast<float *>(wprev);
-        evk::cheb_vec<float>(st(), A32, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
-                             dst, zf, ld, 1, coef_dev, deg + 1, j + 1);
-        wprev = wcur;
-        wcur = dst;
+    if (!ctx->use_graphs) {
+      if (prec == EVSL_F32) {
+        evk::to_f32(st(), n, q, q32);
+        recurrence_f32(st(), var);
+      } else {
+        recurrence_f64(st(), var, q);
       }
-      evk::to_f64(st(), n, zf, z);
       return;
     }
+    // stage q_i in the fixed input, then replay the captured recurrence
+    if (prec == EVSL_F32)
+      evk::to_f32(st(), n, q, q32);
+    else
+      HC(ctx, hipMemcpyAsync(qin, q, sizeof(double) * n, hipMemcpyDeviceToDevice, st()));
+    if (!fgx || fg_var != var) {
+      if (fgx) (void)hipGraphExecDestroy(fgx);
+      if (fg) (void)hipGraphDestroy(fg);
+      fgx = nullptr;
+      fg = nullptr;
+      // captured on the context's capture stream (the caller's stream may be
+      // the null stream, which cannot capture), replayed on the context stream
+      hipStream_t cs = capture_stream(ctx);
+      CaptureGuard cg{cs};
+      HC(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      cg.open = true;
+      if (prec == EVSL_F32)
+        recurrence_f32(cs, var);
+      else
+        recurrence_f64(cs, var, qin);
+      cg.open = false;
+      HC(ctx, hipStreamEndCapture(cs, &fg));
+      HC(ctx, hipGraphInstantiate(&fgx, fg, nullptr, nullptr, 0));
+      fg_var = var;
+    }
+    HC(ctx, hipGraphLaunch(fgx, st()));
+  }
+
+  // z = rho(A-hat) q in FP32 (values, vectors and accumulation in float; q
+  // already converted into q32), then widened into z
+  void recurrence_f32(hipStream_t s, int var) {
+    const evk::Csr A32 = csr32();
+    evk::cheb_vec<float>(s, A32, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q32, nullptr, w0f, zf,
+                         ld, 1, coef_dev, deg + 1, 1);
+    const float *wprev = q32;
+    float *wcur = w0f;
+    for (int j = 1; j < deg; ++j) {
+      float *dst = (wprev == q32) ? w1f : const_cast<float *>(wprev);
+      evk::cheb_vec<float>(s, A32, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
+                           dst, zf, ld, 1, coef_dev, deg + 1, j + 1);
+      wprev = wcur;
+      wcur = dst;
+    }
+    evk::to_f64(s, n, zf, z);
+  }
+
+  // z = rho(A-hat) q in FP64
+  void recurrence_f64(hipStream_t s, int var, const double *q) {
     const evk::Csr Ac = to_csr(A);
     // W_1 = (A q - c q)/d; Y = c0 q + c1 W_1
-    evk::cheb_vec<double>(st(), Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z,
-                          ld, 1, coef_dev, deg + 1, 1);
+    evk::cheb_vec<double>(s, Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z, ld,
+                          1, coef_dev, deg + 1, 1);
     // W_{j+1} is written over W_{j-1}; the input q itself is never written
     const double *wprev = q;
     double *wcur = w0;
     for (int j = 1; j < deg; ++j) {
       double *dst = (wprev == q) ? w1 : const_cast<double *>(wprev);
-      evk::cheb_vec<double>(st(), Ac, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
+      evk::cheb_vec<double>(s, Ac, var, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev,
                             dst, z, ld, 1, coef_dev, deg + 1, j + 1);
       wprev = wcur;
       wcur = dst;
@@ -315,13 +388,15 @@ struct Slice {
   // queue the two scalars (alpha_i, beta_{i+1}) for the host.
   void orth_and_queue() {
     const int nb = nlock + i + 1;
-    cgs2(st(), n, nb, B, ld, z, ow);
+    // the three-term recurrence accounts for q_i and q_{i-1} (i > l), or for
+    // q_l and the whole thick-restart block (i == l)
+    cgs_dgks(st(), n, nb, B, ld, z, ow, nlock, i > l ? nlock + i - 1 : nlock);
     evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
     evk::normalize(st(), n, z, col(nb), ow.nrm2, nullptr);
     hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, st(), ow.h1, ow.h2, nlock + i,
-                       ow.nrm2, ow.scal);
+                       ow.nrm2, ow.scal, ow.gate);
     HC(ctx, hipEventRecord(ev2, st()));
-    HC(ctx, hipMemcpyAsync(hostsc, ow.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st()));
+    HC(ctx, hipMemcpyAsync(hostsc, ow.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st()));
   }
 
   // Host part of the step (after the stream has been synchronised).
@@ -331,6 +406,7 @@ struct Slice {
     if (hipEventElapsedTime(&ms2, ev1, ev2) == hipSuccess) t_orth += ms2 * 1e-3;
     its++;
     const double a_i = hostsc[0], b_i = hostsc[1];
+    if (hostsc[2] != 0.0) ++npass2;
     alpha[i] = a_i;
     if (!std::isfinite(a_i) || !std::isfinite(b_i)) fail(EVSL_ESPECTRUM);
     bool end_cycle = false, settled = false;
@@ -832,6 +908,7 @@ struct Slice {
     out->nmv = nmv;
     out->nrestart = nrestart;
     out->npolish = npolish;
+    out->north2 = npass2;
     out->status = status == EVSL_ENOMEM ? EVSL_ENOCONV : status;
     out->t_mv = t_mv;
     out->t_orth = t_orth;
@@ -1190,7 +1267,7 @@ int lanczos_tridiag(evsl_ctx_t ctx, const evsl_csr_t *A, int m, uint64_t seed, i
     evk::col_dots(s, n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
     evk::normalize(s, n, z, Q + (int64_t)(i + 1) * ld, ow.nrm2, nullptr);
     hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, s, ow.h1, ow.h2, i, ow.nrm2,
-                       ow.scal + 2 * i);
+                       ow.scal + 2 * i, nullptr);
     HC(ctx, hipMemcpyAsync(hs + 2 * i, ow.scal + 2 * i, 2 * sizeof(double), hipMemcpyDeviceToHost,
                            s));
     if ((i & 15) == 15 || i == m - 1) {
@@ -1478,18 +1555,6 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
     }
     ~Graphs() { clear(); }
   } graphs;
-  // ends a capture left open by an error, so the stream stays usable
-  struct CaptureGuard {
-    hipStream_t s;
-    bool open = false;
-    ~CaptureGuard() {
-      if (open) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(s, &g);
-        if (g) (void)hipGraphDestroy(g);
-      }
-    }
-  };
   while (true) {
     act.clear();
     for (int q : order)

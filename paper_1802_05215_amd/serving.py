@@ -150,10 +150,13 @@ def footprint_parts(req: Request) -> Dict[str, int]:
     ns = req.nslices
     m, cap = _lan_sizes(req.nev_plan, n)
     cols = cap + m + 1
-    per_slice = 8 * (ld * (cols + 3) + m * m
+    # basis, filter output, two recurrence vectors and the staged input; Ritz
+    # block; partial sums; Gram-Schmidt coefficients, norms and the DGKS gate;
+    # coefficients
+    per_slice = 8 * (ld * (cols + 4) + m * m
                      + max(((n + 1023) // 1024) * (cols + 8),
                            ((n + 2047) // 2048) * (max(m, cap) + 2))
-                     + 2 * (cols + 8) + 3 * m + 16 + 10001)
+                     + 2 * (cols + 8) + 3 * m + 16 + (n + 255) // 256 + 2 + 10001)
     batch = 8 * (3 * n * ns + ns * 10001 + 2 * (ns + 1)) + 8 * 2 * ld * m
     vectors = 8 * n * cap * ns
     parts["library"] = ws + batch + ns * per_slice + vectors

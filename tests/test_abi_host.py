@@ -130,3 +130,34 @@ def test_lspol_matches_oracle(kind):
         assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
     with pytest.raises(ev.EvslError):
         ev.evsl_lspol(kind, 0.0, 1.0, 5)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the size and field offsets
+    the C compiler gives the header's definition."""
+    import ctypes as C
+
+    import paper_1802_05215_amd as pk
+    mirrors = {"evsl_csr_t": pk.CsrT, "evsl_pol_t": pk.PolT, "evsl_lan_opts_t": pk.LanOptsT,
+               "evsl_si_opts_t": pk.SiOptsT, "evsl_eigs_t": pk.EigsT}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "evsl_mi355.h"',
+             'int main(void) {']
+    for name, cls in mirrors.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if ln:
+            a, b, v = ln.split()
+            got[(a, b)] = int(v)
+    for name, cls in mirrors.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])

@@ -347,7 +347,7 @@ def test_batch_graph_replays_equal_eager_launches(ctx, group, own_stream):
     synchronisation between replays); the results must equal, bit for bit,
     those of the same launches issued eagerly. Checked on the null stream and
     on a stream of its own, with one group of three slices and with groups of
-    two and one (the single-slice group stays eager)."""
+    two and one (a one-slice group replays the single-vector filter graph)."""
     A = I.laplacian(24, 2, pot_seed=1)
     lo, hi = oracle.lanczos_bounds(A, 80, 3)
     cuts = [1.0, 1.3, 1.6, 1.9]
@@ -375,6 +375,33 @@ def test_batch_graph_replays_equal_eager_launches(ctx, group, own_stream):
         for (l0, r0, y0, n0), (l1, r1, y1, n1) in zip(eager, run):
             assert n0 == n1
             assert np.array_equal(l0, l1) and np.array_equal(r0, r1) and np.array_equal(y0, y1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_slice_graph_replays_equal_eager_launches(ctx, prec):
+    """The single-slice solver stages each Lanczos vector in a fixed buffer
+    and replays the captured degree-step launches; every replay (two solves,
+    hundreds of replays each, with the orthogonalisation and host
+    synchronisation in between) must give, bit for bit, what the same
+    launches give issued one by one."""
+    A = I.laplacian(30, 2, pot_seed=2)
+    lo, hi = oracle.lanczos_bounds(A, 80, 3)
+    iv = [1.0, 1.4, lo, hi]
+    pol = _pol(iv)
+    p = ev.EVSL_F32 if prec == "f32" else ev.EVSL_F64
+    opts = ev.lan_opts(tol=1e-9 if prec == "f64" else 1e-8, seed=5, nev_est=60, prec=p)
+    Ad = ev.DeviceCsr.from_host(A)
+    res = {}
+    for on in (False, True, True):
+        ctx.set_graphs(on)
+        lam, Y, r, st = ev.evsl_filtered_lanczos(ctx, Ad, iv, pol, opts)
+        res.setdefault(on, []).append((lam, r, Y.cpu().numpy(), st["niter"]))
+    ctx.set_graphs(True)
+    l0, r0, y0, n0 = res[False][0]
+    assert len(l0) > 20
+    for l1, r1, y1, n1 in res[True]:
+        assert n0 == n1
+        assert np.array_equal(l0, l1) and np.array_equal(r0, r1) and np.array_equal(y0, y1)
 
 
 def test_autotune_picks_a_width_and_batches_still_agree(ctx):

@@ -181,7 +181,9 @@ def one_step(ctx, ev, Ad, args):
     lams, ress, per_slice = [], [], []
     for q, (lam, Y, res, st) in enumerate(outs):
         last = sel[q] == args.nslices - 1
-        keep = (lam >= ivs[q][0]) & ((lam < ivs[q][1]) | last) & (res <= args.tol)
+        # a slice that starts at the lower spectrum bound owns everything below it
+        keep = ((lam >= ivs[q][0]) | (ivs[q][0] <= ivs[q][2])) & ((lam < ivs[q][1]) | last) \
+            & (res <= args.tol)
         lams.append(lam[keep])
         ress.append(res[keep])
         per_slice.append(dict(slice=sel[q], deg=pols[q].deg, nev=int(keep.sum()), niter=st["niter"],
@@ -803,7 +805,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "traffic_bytes_per_launch": None,
-            "kernel": "k_cheb_blk<double, STEP_NEXT> (filter degree step)",
+            "kernel": "k_cheb_blk_lds<double, STEP_CLEN> (Clenshaw filter degree step)",
             "bytes_per_launch": per_launch_bytes,
             "avg_launch_us": fs["seconds"] / max(fs["launches"], 1) * 1e6,
             "launches": fs["launches"],

@@ -510,7 +510,13 @@ int or_filtered_lanczos(int64_t n, const int32_t *rp, const int32_t *ci, const d
                         const or_lan_opts *opt, double *lam, double *res, double *Y,
                         or_lan_stats *st) {
   memset(st, 0, sizeof(*st));
-  double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
+  /* a slice that reaches a bound of the spectrum owns every eigenvalue
+   * beyond it: the bound is an estimate, within rounding of the extreme
+   * eigenvalue when the bounding Lanczos run has converged */
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
   double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
   double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
   int m = opt->m;
@@ -708,7 +714,13 @@ int or_filtered_lanczos_nr(int64_t n, const int32_t *rp, const int32_t *ci, cons
                            const or_lan_opts *opt, double *lam, double *res, double *Y,
                            or_lan_stats *st) {
   memset(st, 0, sizeof(*st));
-  double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
+  /* a slice that reaches a bound of the spectrum owns every eigenvalue
+   * beyond it: the bound is an estimate, within rounding of the extreme
+   * eigenvalue when the bounding Lanczos run has converged */
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
   double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
   double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
   int m = opt->m;
@@ -855,7 +867,13 @@ int or_filtered_subspace(int64_t n, const int32_t *rp, const int32_t *ci, const 
                          const or_si_opts *opt, double *lam, double *res, double *Y,
                          or_lan_stats *st) {
   memset(st, 0, sizeof(*st));
-  const double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
+  /* a slice that reaches a bound of the spectrum owns every eigenvalue
+   * beyond it: the bound is an estimate, within rounding of the extreme
+   * eigenvalue when the bounding Lanczos run has converged */
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
   const double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
   const double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
   const int b = opt->block;
@@ -1164,7 +1182,13 @@ int or_filtered_lanczos_gen(int64_t n, const int32_t *rp, const int32_t *ci, con
                             const or_lan_opts *opt, double *lam, double *res, double *Y,
                             or_lan_stats *st) {
   memset(st, 0, sizeof(*st));
-  const double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
+  /* a slice that reaches a bound of the spectrum owns every eigenvalue
+   * beyond it: the bound is an estimate, within rounding of the extreme
+   * eigenvalue when the bounding Lanczos run has converged */
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
   const double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
   const double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
   int m = opt->m;

@@ -302,8 +302,12 @@ int evsl_filtered_lanczos_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_cs
   if (A->dtype != EVSL_F64 || B->dtype != EVSL_F64) return EVSL_ENOTIMPL;
   if (opt && (opt->prec != EVSL_F64 || opt->method == EVSL_LAN_TR)) return EVSL_ENOTIMPL;
   const double t0 = now_s();
-  const double tlo = intv[0], thi = intv[1], lmin = intv[2], lmax = intv[3];
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
   if (!(thi > tlo) || !(lmax > lmin) || !pol->coef || pol->deg < 1) return EVSL_EINVAL;
+  // a slice that reaches a bound of the spectrum owns every eigenvalue beyond it
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
   const double normA = std::max(std::fabs(lmin), std::fabs(lmax));
   GenSolver g;
   g.filtered = true;

@@ -12,21 +12,18 @@
 
 namespace evh {
 
-int sym_eig(int m, double *A, double *w, double *V) {
-  if (m <= 0) return -1;
-  if (m == 1) {
-    w[0] = A[0];
-    if (V) V[0] = 1.0;
-    return 0;
-  }
+namespace {
+
+// Householder tridiagonalisation of the symmetric m x m A (column-major,
+// overwritten): reflector k = I - beta_k v_k v_k^T zeroes column k below the
+// subdiagonal (v_k on rows k+1..m-1). d, e receive the tridiagonal. When R is
+// given, v_k goes to column k of R and beta_k to betas[k]; when V is given it
+// accumulates V <- V H_k.
+void householder(int m, double *A, double *d, double *e, double *R, double *betas, double *V) {
   auto a = [&](int i, int j) -> double & { return A[i + (size_t)j * m]; };
-  if (V) {
-    std::fill(V, V + (size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) V[i + (size_t)i * m] = 1.0;
-  }
   std::vector<double> v(m), p(m), q(m);
-  // --- Householder tridiagonalisation: column k below the subdiagonal is zeroed
   for (int k = 0; k + 2 < m; ++k) {
+    if (betas) betas[k] = 0.0;
     const int len = m - k - 1;
     double sig = 0.0;
     for (int i = 0; i < len; ++i) sig += a(k + 1 + i, k) * a(k + 1 + i, k);
@@ -39,36 +36,78 @@ int sym_eig(int m, double *A, double *w, double *V) {
     for (int i = 0; i < len; ++i) vv += v[i] * v[i];
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
-    // p = beta * A22 v
-    for (int i = 0; i < len; ++i) {
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += a(k + 1 + i, k + 1 + j) * v[j];
-      p[i] = beta * s;
+    // p = beta * A22 v, column by column (A is column-major)
+    std::fill(p.begin(), p.begin() + len, 0.0);
+    for (int j = 0; j < len; ++j) {
+      const double vj = v[j];
+      const double *col = &a(k + 1, k + 1 + j);
+      for (int i = 0; i < len; ++i) p[i] += col[i] * vj;
     }
     double pv = 0.0;
-    for (int i = 0; i < len; ++i) pv += p[i] * v[i];
+    for (int i = 0; i < len; ++i) {
+      p[i] *= beta;
+      pv += p[i] * v[i];
+    }
     const double kk = 0.5 * beta * pv;
     for (int i = 0; i < len; ++i) q[i] = p[i] - kk * v[i];
-    for (int j = 0; j < len; ++j)
-      for (int i = 0; i < len; ++i) a(k + 1 + i, k + 1 + j) -= v[i] * q[j] + q[i] * v[j];
+    // A22 <- A22 - v q^T - q v^T
+    for (int j = 0; j < len; ++j) {
+      const double vj = v[j], qj = q[j];
+      double *col = &a(k + 1, k + 1 + j);
+      for (int i = 0; i < len; ++i) col[i] -= v[i] * qj + q[i] * vj;
+    }
     a(k + 1, k) = alpha;
     a(k, k + 1) = alpha;
-    for (int i = 1; i < len; ++i) {
-      a(k + 1 + i, k) = 0.0;
-      a(k, k + 1 + i) = 0.0;
+    for (int i = 1; i < len; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+    if (R) {
+      for (int i = 0; i < len; ++i) R[(k + 1 + i) + (size_t)k * m] = v[i];
+      betas[k] = beta;
     }
     if (V) {  // V <- V (I - beta v v^T) on columns k+1..m-1
       for (int r = 0; r < m; ++r) {
-        double s = 0.0;
-        for (int i = 0; i < len; ++i) s += V[r + (size_t)(k + 1 + i) * m] * v[i];
-        s *= beta;
-        for (int i = 0; i < len; ++i) V[r + (size_t)(k + 1 + i) * m] -= s * v[i];
+        double t = 0.0;
+        for (int i = 0; i < len; ++i) t += V[r + (size_t)(k + 1 + i) * m] * v[i];
+        t *= beta;
+        for (int i = 0; i < len; ++i) V[r + (size_t)(k + 1 + i) * m] -= t * v[i];
       }
     }
   }
-  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
   for (int i = 0; i < m; ++i) d[i] = a(i, i);
   for (int i = 0; i + 1 < m; ++i) e[i] = a(i + 1, i);
+}
+
+// z <- H_0 H_1 ... H_{m-3} z for nvec columns of Z (leading dimension ldz,
+// rows 0..m-1): the reflectors from the last to the first.
+void apply_reflectors(int m, const double *R, const double *betas, int nvec, double *Z,
+                      int64_t ldz) {
+  for (int k = m - 3; k >= 0; --k) {
+    if (betas[k] == 0.0) continue;
+    const double *vk = R + (size_t)k * m;
+    for (int c = 0; c < nvec; ++c) {
+      double *z = Z + (size_t)c * ldz;
+      double t = 0.0;
+      for (int i = k + 1; i < m; ++i) t += vk[i] * z[i];
+      t *= betas[k];
+      for (int i = k + 1; i < m; ++i) z[i] -= t * vk[i];
+    }
+  }
+}
+
+}  // namespace
+
+int sym_eig(int m, double *A, double *w, double *V) {
+  if (m <= 0) return -1;
+  if (m == 1) {
+    w[0] = A[0];
+    if (V) V[0] = 1.0;
+    return 0;
+  }
+  if (V) {
+    std::fill(V, V + (size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) V[i + (size_t)i * m] = 1.0;
+  }
+  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+  householder(m, A, d.data(), e.data(), nullptr, nullptr, V);
   return tridiag_eig(m, d.data(), e.data(), w, V);
 }
 
@@ -97,7 +136,8 @@ int tridiag_eig(int m, double *d, double *e, double *w, double *V) {
     double x = d[lo] - mu, z = e[lo];
     double bulge = 0.0;
     for (int k = lo; k < hi; ++k) {
-      const double r = std::hypot(x, z);
+      // |x|, |z| are of the order of ||T||: no scaling needed against overflow
+      const double r = std::sqrt(x * x + z * z);
       const double c = r == 0.0 ? 1.0 : x / r;
       const double s = r == 0.0 ? 0.0 : -z / r;
       if (k > lo) e[k - 1] = r;
@@ -274,64 +314,67 @@ void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const do
 // w[m - nsel .. m - 1]; returns nsel.
 int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel) {
   if (m <= 0) return -1;
-  auto a = [&](int i, int j) -> double & { return A[i + (size_t)j * m]; };
-  std::vector<double> R((size_t)m * m, 0.0), betas(m, 0.0);  // reflector k in column k
-  std::vector<double> v(m), p(m), q(m);
-  for (int k = 0; k + 2 < m; ++k) {
-    const int len = m - k - 1;
-    double sig = 0.0;
-    for (int i = 0; i < len; ++i) sig += a(k + 1 + i, k) * a(k + 1 + i, k);
-    if (sig == 0.0) continue;
-    const double x0 = a(k + 1, k);
-    const double alpha = x0 >= 0 ? -std::sqrt(sig) : std::sqrt(sig);
-    for (int i = 0; i < len; ++i) v[i] = a(k + 1 + i, k);
-    v[0] -= alpha;
-    double vv = 0.0;
-    for (int i = 0; i < len; ++i) vv += v[i] * v[i];
-    if (vv == 0.0) continue;
-    const double beta = 2.0 / vv;
-    for (int i = 0; i < len; ++i) {
-      double t = 0.0;
-      for (int j = 0; j < len; ++j) t += a(k + 1 + i, k + 1 + j) * v[j];
-      p[i] = beta * t;
-    }
-    double pv = 0.0;
-    for (int i = 0; i < len; ++i) pv += p[i] * v[i];
-    const double kk = 0.5 * beta * pv;
-    for (int i = 0; i < len; ++i) q[i] = p[i] - kk * v[i];
-    for (int j = 0; j < len; ++j)
-      for (int i = 0; i < len; ++i) a(k + 1 + i, k + 1 + j) -= v[i] * q[j] + q[i] * v[j];
-    a(k + 1, k) = alpha;
-    a(k, k + 1) = alpha;
-    for (int i = 1; i < len; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
-    for (int i = 0; i < len; ++i) R[(k + 1 + i) + (size_t)k * m] = v[i];
-    betas[k] = beta;
-  }
+  std::vector<double> R((size_t)m * m, 0.0), betas(std::max(m, 1), 0.0);
   std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
-  for (int i = 0; i < m; ++i) d[i] = a(i, i);
-  for (int i = 0; i + 1 < m; ++i) e[i] = a(i + 1, i);
+  householder(m, A, d.data(), e.data(), R.data(), betas.data(), nullptr);
+  const int nsel = tridiag_eig_sel(m, d.data(), e.data(), w, thr, Vsel);
+  if (nsel > 0) apply_reflectors(m, R.data(), betas.data(), nsel, Vsel, m);
+  return nsel;
+}
+
+int tridiag_eig_sel(int m, const double *d, const double *e, double *w, double thr,
+                    double *Vsel) {
+  if (m <= 0) return -1;
   {
-    std::vector<double> d2(d), e2(e);
+    std::vector<double> d2(d, d + m), e2(std::max(m - 1, 1), 0.0);
+    std::copy(e, e + (m - 1), e2.begin());
     tridiag_eig(m, d2.data(), e2.data(), w, nullptr);
   }
   int first = m;
   while (first > 0 && w[first - 1] >= thr) --first;
   const int nsel = m - first;
-  if (nsel == 0) return 0;
-  tridiag_eigvecs(m, d.data(), e.data(), nsel, w + first, Vsel);
-  // V = H_0 H_1 ... H_{m-3} Z, applied from the last reflector to the first
-  for (int k = m - 3; k >= 0; --k) {
-    if (betas[k] == 0.0) continue;
-    const double *vk = R.data() + (size_t)k * m;
-    for (int c = 0; c < nsel; ++c) {
-      double *z = Vsel + (size_t)c * m;
-      double t = 0.0;
-      for (int i = k + 1; i < m; ++i) t += vk[i] * z[i];
-      t *= betas[k];
-      for (int i = k + 1; i < m; ++i) z[i] -= t * vk[i];
-    }
-  }
+  if (nsel > 0) tridiag_eigvecs(m, d, e, nsel, w + first, Vsel);
   return nsel;
+}
+
+void ArrowForm::reduce(int nl, const double *th, const double *s, double al, double *d,
+                       double *e) {
+  l = nl;
+  const int L = l + 1;
+  // the block in the order [l, 0, 1, ..., l-1]: index l first, so that the
+  // reflectors (which act on rows 1..L-1) leave it fixed
+  std::vector<double> M((size_t)L * L, 0.0);
+  M[0] = al;
+  for (int j = 0; j < l; ++j) {
+    M[(j + 1)] = s[j];
+    M[(size_t)(j + 1) * L] = s[j];
+    M[(j + 1) + (size_t)(j + 1) * L] = th[j];
+  }
+  R.assign((size_t)L * L, 0.0);
+  betas.assign(std::max(L, 1), 0.0);
+  std::vector<double> dm(L), em(std::max(L - 1, 1), 0.0);
+  if (L == 1) {
+    dm[0] = al;
+  } else {
+    householder(L, M.data(), dm.data(), em.data(), R.data(), betas.data(), nullptr);
+  }
+  // reversed, so that index l comes last and couples to index l+1 of T
+  for (int p = 0; p < L; ++p) d[p] = dm[L - 1 - p];
+  for (int p = 0; p + 1 < L; ++p) e[p] = em[L - 2 - p];
+}
+
+void ArrowForm::back(int nvec, double *Y, int64_t ldy) const {
+  const int L = l + 1;
+  std::vector<double> u((size_t)L * nvec);
+  for (int c = 0; c < nvec; ++c)
+    for (int p = 0; p < L; ++p) u[(size_t)c * L + (L - 1 - p)] = Y[p + (size_t)c * ldy];
+  if (L > 2) apply_reflectors(L, R.data(), betas.data(), nvec, u.data(), L);
+  for (int c = 0; c < nvec; ++c) {
+    double *y = Y + (size_t)c * ldy;
+    const double *uc = u.data() + (size_t)c * L;
+    y[l] = uc[0];
+    for (int j = 0; j < l; ++j) y[j] = uc[j + 1];
+  }
 }
 
 }  // namespace evh

@@ -1,6 +1,7 @@
 // Host-side polynomial work: damping, find_pol, KPM count, slicer.
 #pragma once
 #include <cstdint>
+#include <vector>
 
 namespace evh {
 
@@ -43,6 +44,24 @@ int tridiag_eig(int m, double *d, double *e, double *w, double *V);
 // All eigenvalues of the symmetric A (overwritten), ascending, and the
 // eigenvectors of those >= thr (Vsel, m x nsel, same order); returns nsel.
 int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel);
+// The same for a tridiagonal (d, e), not overwritten: QR for the eigenvalues,
+// inverse iteration for the selected eigenvectors.
+int tridiag_eig_sel(int m, const double *d, const double *e, double *w, double thr,
+                    double *Vsel);
+// The projected matrix after a thick restart (Section 2.3.2, arrowhead form):
+// diagonal th[0..l-1], their couplings s[0..l-1] to index l, T(l, l) = al,
+// then tridiagonal from index l on. reduce() brings the (l+1) x (l+1) leading
+// block to tridiagonal form by reflectors that leave index l fixed, ordered so
+// that index l comes last (d: l+1 values, e: l); with T's coupling of l to
+// l+1 and the rest of T this is one tridiagonal matrix with T's eigenvalues.
+// back() maps rows 0..l of nvec eigenvectors of that tridiagonal (leading
+// dimension ldy) to eigenvectors of T; rows l+1.. are unchanged.
+struct ArrowForm {
+  int l = -1;
+  std::vector<double> R, betas;
+  void reduce(int nl, const double *th, const double *s, double al, double *d, double *e);
+  void back(int nvec, double *Y, int64_t ldy) const;
+};
 // Eigenvectors of the tridiagonal (d, e) for nsel eigenvalues lam (ascending)
 // by inverse iteration; Z is m x nsel column-major.
 void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const double *lam,

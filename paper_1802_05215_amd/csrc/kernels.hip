@@ -265,7 +265,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
                                                   const double *__restrict__ coef, int cld,
                                                   int jnext, const T *__restrict__ Vd,
                                                   double *partial) {
-  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT);
+  constexpr bool IS_CLEN = (KIND == STEP_CLEN);
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT || IS_CLEN);
   constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
   constexpr bool Y_INIT = (KIND == STEP_FIRST);
   constexpr bool HAS_DOT = (KIND == STEP_KPM_FIRST || KIND == STEP_KPM_NEXT);
@@ -287,10 +288,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
   double dacc = 0.0;
   if (active) {
     T c0 = 0, c1 = 0;
-    if (HAS_Y) {
-      c1 = (T)coef[(int64_t)col * cld + jnext];
-      if (Y_INIT) c0 = (T)coef[(int64_t)col * cld];
-    }
+    if (HAS_Y || IS_CLEN) c1 = (T)coef[(int64_t)col * cld + jnext];
+    if (Y_INIT) c0 = (T)coef[(int64_t)col * cld];
     const int rbeg = blockIdx.x * rows_per_wg;
     const int rend = min(rbeg + rows_per_wg, n);
     for (int r = rbeg + rsub; r < rend; r += R0) {
@@ -301,6 +300,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
       const T w = W[e];
       T wn = s1 * acc + s0 * w;
       if (HAS_PREV) wn -= Wp[e];
+      if (IS_CLEN) wn += c1 * Vd[e];
       Wn[e] = wn;
       if (HAS_Y) {
         const T y = Y_INIT ? c0 * w : Y[e];
@@ -334,7 +334,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
                                                       double *partial) {
   typedef T vt __attribute__((ext_vector_type(VEC)));
   constexpr int CAP = 1792;
-  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT);
+  constexpr bool IS_CLEN = (KIND == STEP_CLEN);
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || KIND == STEP_KPM_NEXT || IS_CLEN);
   constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
   constexpr bool Y_INIT = (KIND == STEP_FIRST);
   constexpr bool HAS_DOT = (KIND == STEP_KPM_FIRST || KIND == STEP_KPM_NEXT);
@@ -383,10 +384,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
     vt c0 = (T)0, c1 = (T)0;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-      if (HAS_Y) {
-        c1[v] = (T)coef[(col + v) * cld + jnext];
-        if (Y_INIT) c0[v] = (T)coef[(col + v) * cld];
-      }
+      if (HAS_Y || IS_CLEN) c1[v] = (T)coef[(col + v) * cld + jnext];
+      if (Y_INIT) c0[v] = (T)coef[(col + v) * cld];
     }
     const T *wc = W + col;
     for (int rl = rsub; rl < nr; rl += R0) {
@@ -413,6 +412,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
       const vt w = *(const vt *)(W + e);
       vt wn = s1 * acc + s0 * w;
       if (HAS_PREV) wn -= *(const vt *)(Wp + e);
+      if (IS_CLEN) wn += c1 * *(const vt *)(Vd + e);
       *(vt *)(Wn + e) = wn;
       if (HAS_Y) {
         const vt y = Y_INIT ? c0 * w : *(const vt *)(Y + e);
@@ -511,6 +511,7 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
     case STEP_FIRST: EVK_LAUNCH_BLK(STEP_FIRST); break;
     case STEP_NEXT: EVK_LAUNCH_BLK(STEP_NEXT); break;
     case STEP_KPM_FIRST: EVK_LAUNCH_BLK(STEP_KPM_FIRST); break;
+    case STEP_CLEN: EVK_LAUNCH_BLK(STEP_CLEN); break;
     default: EVK_LAUNCH_BLK(STEP_KPM_NEXT); break;
   }
 #undef EVK_LAUNCH_BLK
@@ -524,6 +525,22 @@ template void cheb_blk<double>(hipStream_t, const Csr &, int, double, double, co
 template void cheb_blk<float>(hipStream_t, const Csr &, int, double, double, const float *,
                               const float *, float *, float *, int64_t, int, const double *, int,
                               int, const float *, double *);
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_fill_zero(int64_t count, T *p) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < count) p[i] = (T)0;
+}
+
+template <typename T>
+void fill_zero(hipStream_t s, int64_t count, T *p) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3((unsigned)((count + TPB - 1) / TPB)), dim3(TPB), 0, s,
+                     count, p);
+}
+
+template void fill_zero<double>(hipStream_t, int64_t, double *);
+template void fill_zero<float>(hipStream_t, int64_t, float *);
 
 // ---------------------------------------------------------------- gather / scatter
 // blk (row-major, value type TB) <-> FP64 columns given by a device pointer array.

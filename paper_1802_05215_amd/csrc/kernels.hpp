@@ -20,7 +20,15 @@ struct Csr {
 //   FIRST: Wn = s1 * A W + s0 * W, Y = c0 W + c1 Wn    (s1 = 1/d, s0 = -c/d)
 //   NEXT : Wn = s1 * A W + s0 * W - Wp, Y += c Wn     (s1 = 2/d, s0 = -2c/d)
 // Wn may alias Wp (each element is read, then written, by one thread).
-enum StepKind { STEP_PLAIN = 0, STEP_FIRST = 1, STEP_NEXT = 2, STEP_KPM_FIRST = 3, STEP_KPM_NEXT = 4 };
+enum StepKind {
+  STEP_PLAIN = 0,
+  STEP_FIRST = 1,
+  STEP_NEXT = 2,
+  STEP_KPM_FIRST = 3,
+  STEP_KPM_NEXT = 4,
+  // Clenshaw step: Wn = coef[col][jnext] Vd + s1 A W + s0 W - Wp (Wn may be Wp)
+  STEP_CLEN = 5
+};
 
 // Single vectors stored as columns of a column-major array (column stride ld);
 // grid.y runs over ncol columns. coef: device table, column c uses
@@ -87,6 +95,9 @@ void normalize_cols(hipStream_t s, int n, int ncol, double *X, int64_t ld, const
 // C = A B: A n x K column-major (lda), B K x N column-major (ldb), C n x N (ldc).
 void gemm_nn(hipStream_t s, int n, int K, int N, const double *A, int64_t lda, const double *B,
              int64_t ldb, double *C, int64_t ldc);
+// p[0 .. count) = 0 (a kernel, so that it can be captured in a graph)
+template <typename T>
+void fill_zero(hipStream_t s, int64_t count, T *p);
 // Counter-based random numbers (SplitMix64 output index + 1 from state seed).
 void rademacher(hipStream_t s, int n, int nvec, uint64_t seed, double *V);
 void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double *x);

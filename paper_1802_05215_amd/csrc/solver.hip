@@ -126,6 +126,9 @@ struct Slice {
   // host state
   std::vector<double> alpha, beta;  // alpha[i], beta[i] = coupling (i, i+1)
   std::vector<double> th_tr, s_tr;  // thick-restart diagonal and arrow
+  evh::ArrowForm arrow;               // reduced thick-restart block of this cycle
+  std::vector<double> arrow_d, arrow_e;
+  bool arrow_ok = false;
   std::vector<double> lam, res;     // locked pairs in lock order
   int nlock = 0, l = 0, i = 0, its = 0, nmv = 0, nrand = 0, nocand = 0, nrestart = 0;
   int npass2 = 0;  // Lanczos steps whose reorthogonalisation took a second pass
@@ -174,6 +177,11 @@ struct Slice {
     lmax = intv[3];
     normA = std::max(std::fabs(lmin), std::fabs(lmax));
     if (!(thi > tlo) || !(lmax > lmin) || !pol || !pol->coef || pol->deg < 1) fail(EVSL_EINVAL);
+    // a slice that reaches a bound of the spectrum owns every eigenvalue
+    // beyond it: the bound is an estimate, which can sit within rounding of
+    // the extreme eigenvalue
+    if (tlo <= lmin) tlo = -INFINITY;
+    if (thi >= lmax) thi = INFINITY;
     cc = 0.5 * (lmax + lmin);
     dd = 0.5 * (lmax - lmin);
     if (std::fabs(pol->cc - cc) > 1e-12 * (1 + std::fabs(cc)) ||
@@ -424,16 +432,9 @@ struct Slice {
     }
     if (!end_cycle && ((i + 1) - l) % ncycle == 0) {
       const int k = i + 1;
-      std::vector<double> w(k);
-      if (l == 0) {
-        // no thick-restart block: T is tridiagonal, O(k^2) without vectors
-        std::vector<double> d(alpha.begin(), alpha.begin() + k), e(std::max(k - 1, 1), 0.0);
-        std::copy(beta.begin(), beta.begin() + (k - 1), e.begin());
-        evh::tridiag_eig(k, d.data(), e.data(), w.data(), nullptr);
-      } else {
-        std::vector<double> T = build_T(k);
-        evh::sym_eig(k, T.data(), w.data(), nullptr);
-      }
+      std::vector<double> w(k), d, e;
+      tri_form(k, d, e);  // O(k^2) without vectors
+      evh::tridiag_eig(k, d.data(), e.data(), w.data(), nullptr);
       check_filtered(w);
       t_old = t_new;
       t_new = 0.0;
@@ -466,25 +467,27 @@ struct Slice {
     }
   }
 
-  // T of dimension k: thick-restart arrowhead block then tridiagonal.
-  std::vector<double> build_T(int k) {
-    std::vector<double> T((size_t)k * k, 0.0);
-    for (int j = 0; j < l && j < k; ++j) {
-      T[j + (size_t)j * k] = th_tr[j];
-      if (l < k) {
-        T[j + (size_t)l * k] = s_tr[j];
-        T[l + (size_t)j * k] = s_tr[j];
+  // T of dimension k (k > l) as one tridiagonal, d (k values) and e (k - 1):
+  // the thick-restart block (arrowhead: the Ritz values th_tr coupled to
+  // index l by s_tr) through its reduced form, computed once per cycle, then
+  // the coefficients of the Lanczos steps since the restart.
+  void tri_form(int k, std::vector<double> &d, std::vector<double> &e) {
+    d.assign(k, 0.0);
+    e.assign(std::max(k - 1, 1), 0.0);
+    if (l > 0) {
+      if (!arrow_ok) {
+        arrow_d.assign(l + 1, 0.0);
+        arrow_e.assign(std::max(l, 1), 0.0);
+        arrow.reduce(l, th_tr.data(), s_tr.data(), alpha[l], arrow_d.data(), arrow_e.data());
+        arrow_ok = true;
       }
+      std::copy(arrow_d.begin(), arrow_d.begin() + (l + 1), d.begin());
+      std::copy(arrow_e.begin(), arrow_e.begin() + l, e.begin());
     }
-    for (int r = l; r < k; ++r) {
-      T[r + (size_t)r * k] = alpha[r];
-      if (r + 1 < k) {
-        T[r + (size_t)(r + 1) * k] = beta[r];
-        T[(r + 1) + (size_t)r * k] = beta[r];
-      }
-    }
-    return T;
+    for (int r = l > 0 ? l + 1 : 0; r < k; ++r) d[r] = alpha[r];
+    for (int r = l; r + 1 < k; ++r) e[r] = beta[r];
   }
+
 
   // Non-restart form: Ritz vectors of the Ritz values >= bar of T_dim, in
   // chunks of cmax; those with a Rayleigh quotient in the slice and residual
@@ -564,8 +567,12 @@ struct Slice {
     const double lock_tol = prec == EVSL_F32 ? std::max(tol, tol_lo) : tol;
     // all Ritz values, and the eigenvectors of T for the candidates only
     // (Ritz values >= bar); Ysel column j - first belongs to Ritz value j
-    std::vector<double> T = build_T(dim), w(dim), Ysel((size_t)dim * dim);
-    const int first = dim - evh::sym_eig_sel(dim, T.data(), w.data(), bar, Ysel.data());
+    std::vector<double> d, e, w(dim), Ysel((size_t)dim * dim);
+    tri_form(dim, d, e);
+    const int nsel = evh::tridiag_eig_sel(dim, d.data(), e.data(), w.data(), bar, Ysel.data());
+    if (l > 0 && nsel > 0) arrow.back(nsel, Ysel.data(), dim);
+    arrow_ok = false;  // the thick-restart block is replaced below
+    const int first = dim - nsel;
     check_filtered(w);
     auto Ycol = [&](int j) { return Ysel.begin() + (size_t)(j - first) * dim; };
     const double beta_last = next_ok ? beta[dim - 1] : 0.0;
@@ -1604,25 +1611,30 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       HC(ctx, hipMemcpyAsync(gp, hg, sizeof(double *) * 2 * gn, hipMemcpyHostToDevice, s));
       const double *gtab = ctab + (size_t)g0 * (km + 1);
       hipStream_t ls = s;  // the stream the group's launches go to (or are captured on)
+      // p(A-hat) V by Clenshaw's recurrence (the same polynomial as eq:Cheb0):
+      // B_{k+1} = B_{k+2} = 0, B_k = c_k V + 2 A-hat B_{k+1} - B_{k+2} for
+      // k = deg..1, p(A-hat) V = c_0 V + A-hat B_1 - B_2. A step reads B_{k+1}
+      // (gathered), B_{k+2} and V and writes B_k over B_{k+2}: four passes over
+      // the block against five for the forward recurrence with its running
+      // sum. Column c is active while k <= deg_c (a prefix, slices being in
+      // non-increasing degree); before that its B entries stay zero.
       auto run_group = [&](auto tag, const evk::Csr &Ag) -> double {
         using T = decltype(tag);
         double gbytes = 0.0;
         T *x0 = (T *)X0, *x1 = (T *)X1, *yb = (T *)Yb;
         evk::gather_cols<T>(ls, n, gn, (const double *const *)gp, x0, gn);
-        evk::cheb_blk<T>(ls, Ag, evk::STEP_FIRST, 1.0 / dd, -cc / dd, x0, nullptr, x1, yb, gn,
-                         std::min(gn, std::max(ncs[1] - g0, 1)), gtab, km + 1, 1, nullptr,
-                         nullptr);
-        gbytes += step_bytes(A, gn, es, 3);
-        // x0 = W_0, x1 = W_1; W_{j+1} is written over W_{j-1}
-        T *wprev = x0, *wcur = x1;
-        for (int j = 1; j < gk; ++j) {
-          const int ncj = std::min(gn, std::max(ncs[j + 1] - g0, 1));
-          evk::cheb_blk<T>(ls, Ag, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev, yb,
-                           gn, ncj, gtab, km + 1, j + 1, nullptr, nullptr);
-          gbytes += step_bytes(A, ncj, es, 5);
-          std::swap(wprev, wcur);
+        evk::fill_zero<T>(ls, (int64_t)n * gn, x1);
+        evk::fill_zero<T>(ls, (int64_t)n * gn, yb);
+        T *bk1 = x1, *bk2 = yb;  // B_{k+1}, B_{k+2}; B_k is written over B_{k+2}
+        for (int k = gk; k >= 0; --k) {
+          const int nck = std::min(gn, std::max(ncs[k] - g0, 1));
+          const double sc = k > 0 ? 2.0 : 1.0;
+          evk::cheb_blk<T>(ls, Ag, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
+                           gn, nck, gtab, km + 1, k, x0, nullptr);
+          gbytes += step_bytes(A, nck, es, 4);
+          std::swap(bk1, bk2);
         }
-        evk::scatter_cols<T>(ls, n, gn, yb, gn, (double *const *)(gp + gn));
+        evk::scatter_cols<T>(ls, n, gn, bk1, gn, (double *const *)(gp + gn));
         return gbytes;
       };
       auto launch_group = [&]() -> double {
@@ -1651,7 +1663,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       } else {
         bytes += launch_group();
       }
-      launches += gk;
+      launches += gk + 1;
     }
     for (int q : act) HC(ctx, hipEventRecord(sl[q].ev1, s));
     tm.stop(launches, bytes);

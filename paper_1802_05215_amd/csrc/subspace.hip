@@ -74,6 +74,9 @@ struct SiSlice {
     thi = intv[1];
     const double lmin = intv[2], lmax = intv[3];
     if (!(thi > tlo) || !(lmax > lmin) || !pol || !pol->coef || pol->deg < 1) fail(EVSL_EINVAL);
+    // a slice that reaches a bound of the spectrum owns every eigenvalue beyond it
+    if (tlo <= lmin) tlo = -INFINITY;
+    if (thi >= lmax) thi = INFINITY;
     normA = std::max(std::fabs(lmin), std::fabs(lmax));
     cc = 0.5 * (lmax + lmin);
     dd = 0.5 * (lmax - lmin);

@@ -373,7 +373,9 @@ class DeviceExecutor:
         outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
         lams, ress, ychk = [], [], []
         for q, (lam, Y, res, st) in enumerate(outs):
-            keep = (lam >= ivs[q][0]) & ((lam < ivs[q][1]) | (q == ns - 1)) & (res <= self.tol)
+            # a slice that starts at the lower spectrum bound owns everything below it
+            keep = ((lam >= ivs[q][0]) | (ivs[q][0] <= lo)) & ((lam < ivs[q][1]) | (q == ns - 1)) \
+                & (res <= self.tol)
             lams.append(lam[keep])
             ress.append(res[keep])
             if keep.any():

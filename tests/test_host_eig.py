@@ -27,6 +27,7 @@ def lib():
     L.t_tridiag_eigvecs.argtypes = [C.c_int, dp, dp, C.c_int, dp, dp]
     L.t_tridiag_eigvecs.restype = None
     L.t_sym_eig_sel.argtypes = [C.c_int, dp, dp, C.c_double, dp]
+    L.t_arrow_eig_sel.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_double, dp]
     return L
 
 
@@ -110,3 +111,35 @@ def test_sym_eig_selected_vectors(lib, m, kind):
     sel = w[m - k:]
     assert np.abs(M @ Z - Z * sel).max() <= 1e-10 * np.abs(ref).max()
     assert np.abs(Z.T @ Z - np.eye(k)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("k,l,seed", [(60, 25, 0), (90, 60, 1), (40, 39, 2), (30, 1, 3),
+                                      (12, 11, 4), (200, 120, 5), (3, 1, 6)])
+def test_arrowhead_form_matches_dense(lib, k, l, seed):
+    """Thick-restart matrix (diagonal block with an arrow into index l, then
+    tridiagonal): eigenvalues and the selected eigenvectors through the
+    reduction of the arrowhead block equal a dense eigensolve; the eigenvectors
+    are orthonormal and satisfy T y = theta y."""
+    rng = np.random.default_rng(seed)
+    th = np.sort(rng.uniform(0.3, 1.0, l))[::-1].copy()
+    s = rng.standard_normal(l) * 1e-2 * rng.uniform(0, 1, l) ** 3
+    al = rng.uniform(-0.2, 0.4, k - l)
+    be = rng.uniform(0.05, 0.3, max(k - l - 1, 1))
+    T = np.zeros((k, k))
+    T[np.arange(l), np.arange(l)] = th
+    T[l, :l] = T[:l, l] = s
+    for r in range(l, k):
+        T[r, r] = al[r - l]
+        if r + 1 < k:
+            T[r, r + 1] = T[r + 1, r] = be[r - l]
+    ref = np.linalg.eigvalsh(T)
+    thr = float(np.quantile(ref, 0.7))
+    w = np.empty(k)
+    V = np.zeros((k, k))
+    nsel = lib.t_arrow_eig_sel(k, l, _p(th), _p(s), _p(al), _p(be), _p(w), thr, _p(V))
+    assert np.abs(w - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    assert nsel == int((ref >= thr).sum())
+    Y = V.reshape(k, k)[:nsel].T          # column-major k x nsel
+    lam = w[k - nsel:]
+    assert np.abs(Y.T @ Y - np.eye(nsel)).max() <= 1e-10
+    assert np.abs(T @ Y - Y * lam).max() <= 1e-11

@@ -217,7 +217,10 @@ int evsl_cheb_coeffs(const double intv[4], int damping, double tau, double tau_e
  * type prec (double for EVSL_F64, float for EVSL_F32; with EVSL_F32 A must
  * have dtype EVSL_F32). Column c uses filter pols[col_group[c]] (col_group is
  * a host array of ncols indices < npol); all filters must share cc and dd.
- * Columns ordered by non-increasing degree run fastest. Asynchronous on the
+ * Columns ordered by non-increasing degree run fastest. A single vector
+ * (ncols = ldv = 1) runs the three-term recurrence with its running sum; a
+ * block is evaluated by Clenshaw's recurrence for the same polynomial (four
+ * passes over the block per degree step instead of five). Asynchronous on the
  * context's stream. */
 int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
                       const int32_t *col_group, const void *V, void *Y, int64_t ldv,

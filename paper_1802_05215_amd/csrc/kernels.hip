@@ -612,14 +612,20 @@ void reduce_partials(hipStream_t s, int nw, int ncol, const double *partial, dou
 static constexpr int GEMV_RPL = 16;
 static constexpr int GEMV_ROWS = 64 * GEMV_RPL;
 
-// grid.x: 1024-row chunks; grid.y: groups of GEMV_COLS columns, so that small
-// n still fills the device. Per column a lane sums its rows in increasing
-// order and the wave reduces by a fixed butterfly.
-static constexpr int GEMV_COLS = 64;
+// grid.x: 1024-row chunks; grid.y: groups of cpg columns, so that small n
+// still fills the device: cpg = 64 unless fewer 1024-row chunks than that
+// leave the grid short of about 512 workgroups, down to 4 (one per wave).
+// Per column a lane sums its rows in increasing order and the wave reduces by
+// a fixed butterfly.
+static int gemv_cols_per_group(int nwg, int nb) {
+  const int want = (int)(((int64_t)nb * nwg + 511) / 512);
+  return std::max(4, std::min(64, (want + 3) / 4 * 4));
+}
 
 __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const double *__restrict__ B,
                                                         int64_t ld, const double *__restrict__ z,
-                                                        double *partial, const int *gate) {
+                                                        double *partial, const int *gate,
+                                                        int cpg) {
   if (gate && gate[0] == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.x * GEMV_ROWS;
@@ -630,8 +636,8 @@ __global__ __launch_bounds__(TPB) void k_gemv_t_partial(int n, int nb, const dou
     zr[t] = r < n ? z[r] : 0.0;
   }
   const int nwg = gridDim.x;
-  const int jend = min(nb, (int)(blockIdx.y + 1) * GEMV_COLS);
-  for (int j = blockIdx.y * GEMV_COLS + wave; j < jend; j += 4) {
+  const int jend = min(nb, (int)(blockIdx.y + 1) * cpg);
+  for (int j = blockIdx.y * cpg + wave; j < jend; j += 4) {
     const double *b = B + (int64_t)j * ld;
     double acc = 0.0;
 #pragma unroll
@@ -650,8 +656,9 @@ void gemv_t(hipStream_t s, int n, int nb, const double *B, int64_t ld, const dou
             double *partial, double *h, const int *gate) {
   if (nb <= 0 || n <= 0) return;
   const int nwg = (n + GEMV_ROWS - 1) / GEMV_ROWS;
-  hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg, (nb + GEMV_COLS - 1) / GEMV_COLS), dim3(TPB), 0, s,
-                     n, nb, B, ld, z, partial, gate);
+  const int cpg = gemv_cols_per_group(nwg, nb);
+  hipLaunchKernelGGL(k_gemv_t_partial, dim3(nwg, (nb + cpg - 1) / cpg), dim3(TPB), 0, s, n, nb, B,
+                     ld, z, partial, gate, cpg);
   reduce_partials(s, nwg, nb, partial, 1.0, h, gate);
 }
 

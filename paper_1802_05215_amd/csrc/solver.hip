@@ -1042,6 +1042,7 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, i
   HC(ctx, hipMemsetAsync(ctab, 0, sizeof(double) * (size_t)max_cols * 4, s));
   HC(ctx, hipMemsetAsync(X0, 0, sizeof(double) * blk, s));
   HC(ctx, hipMemsetAsync(X1, 0, sizeof(double) * blk, s));
+  HC(ctx, hipMemsetAsync(Yb, 0, sizeof(double) * blk, s));
   evk::Csr Ac = to_csr(A);
   if (prec == EVSL_F32) {
     float *v32 = (float *)ws(ctx, 25, sizeof(float) * std::max<int64_t>(A->nnz, 1));
@@ -1069,16 +1070,16 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, i
           evk::cheb_vec<float>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb,
                                n, 1, ctab, 4, 1);
         else
-          evk::cheb_blk<float>(s, Ac, evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb, g, g, ctab, 4, 1,
-                               nullptr, nullptr);
+          evk::cheb_blk<float>(s, Ac, evk::STEP_CLEN, sc, 0.0, x1, x0, x0, nullptr, g, g, ctab, 4,
+                               1, yb, nullptr);
       } else {
         double *x0 = (double *)X0, *x1 = (double *)X1, *yb = (double *)Yb;
         if (g == 1)
           evk::cheb_vec<double>(s, Ac, pick_variant(ctx), evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb,
                                 n, 1, ctab, 4, 1);
         else
-          evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, sc, 0.0, x1, x0, x0, yb, g, g, ctab, 4, 1,
-                                nullptr, nullptr);
+          evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc, 0.0, x1, x0, x0, nullptr, g, g, ctab,
+                                4, 1, yb, nullptr);
       }
     }
     HC(ctx, hipEventRecord(e1, s));
@@ -1426,44 +1427,55 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
   const evk::Csr Ac = to_csr(A);
   FilterTimer tm(ctx);
   double bytes = 0.0;
+  int launches = 0;
   auto run = [&](auto tag) {
     using T = decltype(tag);
     const T *v = (const T *)V;
     T *y = (T *)Y, *wa = (T *)Wa, *wb = (T *)Wb;
-    const bool vec = (ncols == 1 && ldv == 1);
-    if (vec) {
+    if (ncols == 1 && ldv == 1) {
+      // one vector: the forward recurrence with its running sum (eq:Cheb0)
       const int var = pick_variant(ctx);
       evk::cheb_vec<T>(s, Ac, var, evk::STEP_FIRST, 1.0 / d0, -c0 / d0, v, nullptr, wa, y, n, 1,
                        ctab, cld, 1);
-    } else {
-      evk::cheb_blk<T>(s, Ac, evk::STEP_FIRST, 1.0 / d0, -c0 / d0, v, nullptr, wa, y, ldv,
-                       active[1], ctab, cld, 1, nullptr, nullptr);
-    }
-    bytes += step_bytes(A, active[1], (int)es, 3);
-    // W_{j+1} is written over W_{j-1}; V itself is never written
-    const T *wprev = v;
-    T *wcur = wa;
-    for (int j = 1; j < kmax; ++j) {
-      const int nc = active[j + 1];
-      T *dst = (wprev == v) ? wb : const_cast<T *>(wprev);
-      if (vec) {
-        const int var = pick_variant(ctx);
+      bytes += step_bytes(A, 1, (int)es, 3);
+      // W_{j+1} is written over W_{j-1}; V itself is never written
+      const T *wprev = v;
+      T *wcur = wa;
+      for (int j = 1; j < kmax; ++j) {
+        T *dst = (wprev == v) ? wb : const_cast<T *>(wprev);
         evk::cheb_vec<T>(s, Ac, var, evk::STEP_NEXT, 2.0 / d0, -2.0 * c0 / d0, wcur, wprev, dst,
                          y, n, 1, ctab, cld, j + 1);
-      } else {
-        evk::cheb_blk<T>(s, Ac, evk::STEP_NEXT, 2.0 / d0, -2.0 * c0 / d0, wcur, wprev, dst, y,
-                         ldv, nc, ctab, cld, j + 1, nullptr, nullptr);
+        bytes += step_bytes(A, 1, (int)es, 5);
+        wprev = wcur;
+        wcur = dst;
       }
-      bytes += step_bytes(A, nc, (int)es, 5);
-      wprev = wcur;
-      wcur = dst;
+      launches = kmax;
+      return;
     }
+    // a block: Clenshaw's recurrence for the same polynomial, B_k = c_k V +
+    // 2 A-hat B_{k+1} - B_{k+2} (B_{kmax+1} = B_{kmax+2} = 0), Y = c_0 V +
+    // A-hat B_1 - B_2; four passes over the block per step. Columns whose
+    // degree is below k have zero coefficients and keep B = 0.
+    evk::fill_zero<T>(s, (int64_t)n * ldv, wa);
+    evk::fill_zero<T>(s, (int64_t)n * ldv, wb);
+    bytes += 2.0 * (double)n * (double)ldv * (double)es;
+    T *bk1 = wa, *bk2 = wb;
+    for (int k = kmax; k >= 0; --k) {
+      const int nc = sorted ? active[k] : ncols;
+      const double sc = k > 0 ? 2.0 : 1.0;
+      T *out = k > 0 ? bk2 : y;
+      evk::cheb_blk<T>(s, Ac, evk::STEP_CLEN, sc / d0, -sc * c0 / d0, bk1, bk2, out, nullptr, ldv,
+                       nc, ctab, cld, k, v, nullptr);
+      bytes += step_bytes(A, nc, (int)es, 4);
+      std::swap(bk1, bk2);
+    }
+    launches = kmax + 1;
   };
   if (prec == EVSL_F64)
     run(double());
   else
     run(float());
-  tm.stop(kmax, bytes);
+  tm.stop(launches, bytes);
   if (hipGetLastError() != hipSuccess) return EVSL_EHIP;
   return EVSL_OK;
   EVSL_GUARD_END

@@ -299,6 +299,27 @@ def test_filtered_lanczos_boundary_slice_triples(ctx):
     assert np.abs(lam - want).max() <= 1e-10 * 12
 
 
+@pytest.mark.parametrize("end", ["low", "high"])
+def test_slice_reaching_a_spectrum_bound_owns_the_extreme_eigenvalue(ctx, end):
+    """As in the oracle: bounds set exactly on the extreme eigenvalues; the
+    boundary slice returns the extreme eigenpair and equals the oracle."""
+    N = 10
+    A = I.laplacian(N, 3)
+    Ad = ev.DeviceCsr.from_host(A)
+    ex = lap_eigs(N, 3)
+    lo, hi = float(ex[0]), float(ex[-1])
+    intv = [lo, 1.4, lo, hi] if end == "low" else [10.6, hi, lo, hi]
+    p = ev.evsl_cheb_coeffs(intv, damping=ev.DAMP_SIGMA, tau=0.8, tau_ext=0.4)
+    want = ex[(ex >= intv[0]) & (ex <= intv[1])]
+    lam, Y, res, st = ev.evsl_filtered_lanczos(ctx, Ad, intv, p,
+                                               ev.lan_opts(tol=1e-10, nev_est=len(want)))
+    assert len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-10 * 12
+    olam, _, _, _ = oracle.filtered_lanczos(A, intv, oracle.find_pol(intv, damping=1),
+                                            tol=1e-10, nev_est=len(want))
+    assert len(olam) == len(lam) and np.abs(olam - lam).max() <= 1e-10 * 12
+
+
 def test_filtered_lanczos_empty_slice(ctx):
     A = I.laplacian(12, 2)
     Ad = ev.DeviceCsr.from_host(A)

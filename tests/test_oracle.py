@@ -349,6 +349,24 @@ def test_filtered_lanczos_boundary_slice_3d():
     assert np.abs(lam - want).max() <= 1e-12 * 12
 
 
+@pytest.mark.parametrize("end", ["low", "high"])
+def test_slice_reaching_a_spectrum_bound_owns_the_extreme_eigenvalue(end):
+    """A slice whose end is the spectrum bound keeps every eigenvalue beyond
+    that end: with the bound set exactly on the extreme eigenvalue (the
+    closed form), the extreme eigenpair is returned, whichever way its
+    computed Rayleigh quotient rounds."""
+    N = 10
+    A = I.laplacian(N, 3)
+    ex = lap_eigs(N, 3)
+    lo, hi = float(ex[0]), float(ex[-1])
+    intv = [lo, 1.4, lo, hi] if end == "low" else [10.6, hi, lo, hi]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_SIGMA, tau_ext=0.4)
+    want = ex[(ex >= intv[0]) & (ex <= intv[1])]
+    lam, Y, res, st = oracle.filtered_lanczos(A, intv, p, tol=1e-10, nev_est=len(want))
+    assert len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-12 * 12
+
+
 def test_filtered_lanczos_empty_slice():
     A = I.laplacian(12, 2)
     ex = lap_eigs(12, 2)

@@ -59,8 +59,9 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_direct(int n, const int *__res
                                                          const T *__restrict__ W, const T *Wp,
                                                          T *Wn, T *Y, int64_t ld,
                                                          const double *__restrict__ coef,
-                                                         int cld, int jnext) {
-  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+                                                         int cld, int jnext, const T *__restrict__ Vd) {
+  constexpr bool IS_CLEN = (KIND == STEP_CLEN);
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || IS_CLEN);
   constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
   constexpr bool Y_INIT = (KIND == STEP_FIRST);
   const int r = blockIdx.x * TPB + threadIdx.x;
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_direct(int n, const int *__res
   const T wr = w[r];
   T wn = s1 * acc + s0 * wr;
   if (HAS_PREV) wn -= Wp[off + r];
+  if (IS_CLEN) wn += (T)coef[(int64_t)blockIdx.y * cld + jnext] * Vd[off + r];
   Wn[off + r] = wn;
   if (HAS_Y) {
     const double *cc = coef + (int64_t)blockIdx.y * cld;
@@ -91,9 +93,10 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds(int n, const int *__restri
                                                       const T *__restrict__ W, const T *Wp, T *Wn,
                                                       T *Y, int64_t ld,
                                                       const double *__restrict__ coef, int cld,
-                                                      int jnext) {
+                                                      int jnext, const T *__restrict__ Vd) {
   constexpr int CAP = 2048;
-  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+  constexpr bool IS_CLEN = (KIND == STEP_CLEN);
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || IS_CLEN);
   constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
   constexpr bool Y_INIT = (KIND == STEP_FIRST);
   __shared__ int s_rp[TPB + 1];
@@ -128,6 +131,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds(int n, const int *__restri
   const T wr = w[r];
   T wn = s1 * acc + s0 * wr;
   if (HAS_PREV) wn -= Wp[off + r];
+  if (IS_CLEN) wn += (T)coef[(int64_t)blockIdx.y * cld + jnext] * Vd[off + r];
   Wn[off + r] = wn;
   if (HAS_Y) {
     const double *cc = coef + (int64_t)blockIdx.y * cld;
@@ -147,9 +151,10 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
                                                        const T *__restrict__ W, const T *Wp, T *Wn,
                                                        T *Y, int64_t ld,
                                                        const double *__restrict__ coef, int cld,
-                                                       int jnext) {
+                                                       int jnext, const T *__restrict__ Vd) {
   constexpr int CAP = 2048;
-  constexpr bool HAS_PREV = (KIND == STEP_NEXT);
+  constexpr bool IS_CLEN = (KIND == STEP_CLEN);
+  constexpr bool HAS_PREV = (KIND == STEP_NEXT || IS_CLEN);
   constexpr bool HAS_Y = (KIND == STEP_FIRST || KIND == STEP_NEXT);
   constexpr bool Y_INIT = (KIND == STEP_FIRST);
   __shared__ int s_rp[TPB + 1];
@@ -196,6 +201,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
   const T wr = w[r];
   T wn = s1 * acc + s0 * wr;
   if (HAS_PREV) wn -= Wp[off + r];
+  if (IS_CLEN) wn += (T)coef[(int64_t)blockIdx.y * cld + jnext] * Vd[off + r];
   Wn[off + r] = wn;
   if (HAS_Y) {
     const double *cc = coef + (int64_t)blockIdx.y * cld;
@@ -207,37 +213,41 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
 template <typename T>
 void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, double s0,
               const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
-              int cld, int jnext) {
+              int cld, int jnext, const T *Vd) {
   if (A.n <= 0 || ncol <= 0) return;
   dim3 grid((A.n + TPB - 1) / TPB, ncol);
   const T *va = (const T *)A.va;
 #define EVK_LAUNCH_VEC(KERN, K)                                                               \
   hipLaunchKernelGGL((KERN<T, K>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, \
-                     Wp, Wn, Y, ld, coef, cld, jnext)
+                     Wp, Wn, Y, ld, coef, cld, jnext, Vd)
   if (variant == 3 || variant == 4) {
     if (variant == 3) {
       switch (kind) {
-        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
-        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
-        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        case STEP_CLEN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_CLEN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
       }
     } else {
       switch (kind) {
-        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
-        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
-        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext); break;
+        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        case STEP_CLEN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_CLEN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
       }
     }
   } else if (variant == 2) {
     switch (kind) {
       case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_PLAIN); break;
       case STEP_FIRST: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_FIRST); break;
+      case STEP_CLEN: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_CLEN); break;
       default: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_NEXT); break;
     }
   } else {
     switch (kind) {
       case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_PLAIN); break;
       case STEP_FIRST: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_FIRST); break;
+      case STEP_CLEN: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_CLEN); break;
       default: EVK_LAUNCH_VEC(k_cheb_vec_direct, STEP_NEXT); break;
     }
   }
@@ -246,10 +256,10 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
 
 template void cheb_vec<double>(hipStream_t, const Csr &, int, int, double, double, const double *,
                                const double *, double *, double *, int64_t, int, const double *,
-                               int, int);
+                               int, int, const double *);
 template void cheb_vec<float>(hipStream_t, const Csr &, int, int, double, double, const float *,
                               const float *, float *, float *, int64_t, int, const double *, int,
-                              int);
+                              int, const float *);
 
 // ---------------------------------------------------------------- filter step, row-major block
 // Row-major n x ld block, the first nc columns active. With nc <= 256 a

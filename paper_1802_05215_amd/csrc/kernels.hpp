@@ -36,7 +36,7 @@ enum StepKind {
 template <typename T>
 void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, double s0,
               const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
-              int cld, int jnext);
+              int cld, int jnext, const T *Vd = nullptr);
 
 // Row-major block n x ld, first nc columns active. For the KPM kinds, Vd is
 // the probe block and partial receives one partial sum of Vd . Wn per

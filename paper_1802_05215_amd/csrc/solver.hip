@@ -302,9 +302,9 @@ struct Slice {
     HC(ctx, hipEventRecord(ev0, st()));
     filter_vector_async();
     HC(ctx, hipEventRecord(ev1, st()));
-    const int es = prec == EVSL_F32 ? 4 : 8;
-    const double b0 = step_bytes(A, 1, es, 3), b1 = step_bytes(A, 1, es, 5);
-    tm.stop(deg, b0 + (deg - 1) * b1);
+    int64_t nl = 0;
+    const double bytes = single_bytes(&nl);
+    tm.stop(nl, bytes);
     nmv += deg;
   }
 
@@ -356,10 +356,47 @@ struct Slice {
     HC(ctx, hipGraphLaunch(fgx, st()));
   }
 
+  // The single-vector filter runs Clenshaw's recurrence (four passes per
+  // degree step, one more launch and two zero fills) when the vector traffic
+  // it saves outweighs the extra launches: n * deg >= 1e7 (about 12 us of
+  // launches against n * deg * 8 bytes at HBM speed); else the forward
+  // recurrence with its running sum.
+  bool single_clenshaw() const { return (double)n * (double)deg >= 1e7; }
+  // algorithmic bytes and launches of one single-vector filter application
+  double single_bytes(int64_t *launches) const {
+    const int es = prec == EVSL_F32 ? 4 : 8;
+    if (single_clenshaw()) {
+      *launches = deg + 1;
+      return 2.0 * (double)n * es + (deg + 1) * step_bytes(A, 1, es, 4);
+    }
+    *launches = deg;
+    return step_bytes(A, 1, es, 3) + (deg - 1) * step_bytes(A, 1, es, 5);
+  }
+
+  // Clenshaw on one vector: B_k = c_k q + 2 A-hat B_{k+1} - B_{k+2}, z = c_0 q +
+  // A-hat B_1 - B_2, with b0/b1 as the two B buffers (zeroed first)
+  template <typename T>
+  void clenshaw_vec(hipStream_t s, const evk::Csr &Ac, int var, const T *q, T *b0, T *b1, T *out) {
+    evk::fill_zero<T>(s, n, b0);
+    evk::fill_zero<T>(s, n, b1);
+    T *bk1 = b0, *bk2 = b1;
+    for (int k = deg; k >= 0; --k) {
+      const double sc = k > 0 ? 2.0 : 1.0;
+      evk::cheb_vec<T>(s, Ac, var, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2,
+                       k > 0 ? bk2 : out, nullptr, ld, 1, coef_dev, deg + 1, k, q);
+      std::swap(bk1, bk2);
+    }
+  }
+
   // z = rho(A-hat) q in FP32 (values, vectors and accumulation in float; q
   // already converted into q32), then widened into z
   void recurrence_f32(hipStream_t s, int var) {
     const evk::Csr A32 = csr32();
+    if (single_clenshaw()) {
+      clenshaw_vec<float>(s, A32, var, q32, w0f, w1f, zf);
+      evk::to_f64(s, n, zf, z);
+      return;
+    }
     evk::cheb_vec<float>(s, A32, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q32, nullptr, w0f, zf,
                          ld, 1, coef_dev, deg + 1, 1);
     const float *wprev = q32;
@@ -377,6 +414,10 @@ struct Slice {
   // z = rho(A-hat) q in FP64
   void recurrence_f64(hipStream_t s, int var, const double *q) {
     const evk::Csr Ac = to_csr(A);
+    if (single_clenshaw()) {
+      clenshaw_vec<double>(s, Ac, var, q, w0, w1, z);
+      return;
+    }
     // W_1 = (A q - c q)/d; Y = c0 q + c1 W_1
     evk::cheb_vec<double>(s, Ac, var, evk::STEP_FIRST, 1.0 / dd, -cc / dd, q, nullptr, w0, z, ld,
                           1, coef_dev, deg + 1, 1);
@@ -1610,8 +1651,9 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
       if (gn == 1) {
         Slice &S = sl[act[g0]];
         S.filter_vector_async();
-        bytes += step_bytes(A, 1, es, 3) + (S.deg - 1) * step_bytes(A, 1, es, 5);
-        launches += S.deg;
+        int64_t nl = 0;
+        bytes += S.single_bytes(&nl);
+        launches += nl;
         continue;
       }
       const double **hg = hsrc + 2 * g0;

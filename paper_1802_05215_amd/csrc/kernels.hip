@@ -835,45 +835,60 @@ void normalize_cols(hipStream_t s, int n, int ncol, double *X, int64_t ld, const
 }
 
 // ---------------------------------------------------------------- C = A B (tall A, small B)
-// 256 rows of C per workgroup and 16 columns per grid.y slice; B staged in LDS
-// 256 rows of K at a time.
-__global__ __launch_bounds__(TPB) void k_gemm_nn(int n, int K, int N, const double *__restrict__ A,
-                                                 int64_t lda, const double *__restrict__ B,
-                                                 int64_t ldb, double *C, int64_t ldc) {
-  __shared__ double Bs[256][16];
-  const int r = blockIdx.x * TPB + threadIdx.x;
-  const int j0 = blockIdx.y * 16;
-  const int nj = min(16, N - j0);
-  double acc[16];
+// FP64 MFMA (v_mfma_f64_16x16x4f64, operand layout as in k_gemm_tn_mfma below):
+// a workgroup owns 64 rows x 64 columns of C, each wavefront 16 rows x the 64
+// columns (four 16 x 16 accumulators). A (column-major) is read straight from
+// memory, 16 consecutive rows per k, once per 64-column block; B is staged in
+// LDS 64 rows of K at a time (zero outside B).
+typedef double v4d __attribute__((ext_vector_type(4)));
+static constexpr int NN_ROWS = 64, NN_COLS = 64, NN_KC = 64;
+
+__global__ __launch_bounds__(TPB) void k_gemm_nn_mfma(int n, int K, int N,
+                                                      const double *__restrict__ A, int64_t lda,
+                                                      const double *__restrict__ B, int64_t ldb,
+                                                      double *C, int64_t ldc) {
+  __shared__ double Bs[NN_KC][NN_COLS + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int rb = blockIdx.x * NN_ROWS + 16 * wave;
+  const int j0 = blockIdx.y * NN_COLS;
+  const int row = rb + i;
+  v4d acc[4];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += 256) {
-    const int kc = min(256, K - k0);
+  for (int t = 0; t < 4; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += NN_KC) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kc * 16; idx += TPB) {
-      const int kk = idx >> 4, jj = idx & 15;
-      Bs[kk][jj] = (jj < nj) ? B[(int64_t)(k0 + kk) + (int64_t)(j0 + jj) * ldb] : 0.0;
+    for (int e = tid; e < NN_KC * NN_COLS; e += TPB) {
+      const int jj = e / NN_KC, kk = e - jj * NN_KC;
+      Bs[kk][jj] = (k0 + kk < K && j0 + jj < N) ? B[(int64_t)(j0 + jj) * ldb + k0 + kk] : 0.0;
     }
     __syncthreads();
-    if (r < n) {
-      const double *a = A + (int64_t)k0 * lda + r;
-      for (int kk = 0; kk < kc; ++kk) {
-        const double av = a[(int64_t)kk * lda];
+    const int kend = min(NN_KC, K - k0);
+    for (int kk = 0; kk < kend; kk += 4) {
+      const int k = k0 + kk + kq;
+      const double a = (row < n && k < K) ? A[(int64_t)k * lda + row] : 0.0;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] += av * Bs[kk][j];
-      }
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[kk + kq][16 * t + i], acc[t], 0, 0, 0);
     }
   }
-  if (r < n) {
-    for (int j = 0; j < nj; ++j) C[(int64_t)(j0 + j) * ldc + r] = acc[j];
+  // lane l, register v: row 4 v + l / 16 of the wave's strip, column l % 16 of tile t
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = j0 + 16 * t + i;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rb + 4 * v + kq;
+      if (r < n && col < N) C[(int64_t)col * ldc + r] = acc[t][v];
+    }
   }
 }
 
 void gemm_nn(hipStream_t s, int n, int K, int N, const double *A, int64_t lda, const double *B,
              int64_t ldb, double *C, int64_t ldc) {
-  if (n <= 0 || N <= 0) return;
-  hipLaunchKernelGGL(k_gemm_nn, dim3((n + TPB - 1) / TPB, (N + 15) / 16), dim3(TPB), 0, s, n, K, N,
-                     A, lda, B, ldb, C, ldc);
+  if (n <= 0 || N <= 0 || K <= 0) return;
+  hipLaunchKernelGGL(k_gemm_nn_mfma, dim3((n + NN_ROWS - 1) / NN_ROWS, (N + NN_COLS - 1) / NN_COLS),
+                     dim3(TPB), 0, s, n, K, N, A, lda, B, ldb, C, ldc);
 }
 
 // ---------------------------------------------------------------- random inputs
@@ -913,7 +928,6 @@ void lanczos_start(hipStream_t s, int n, uint64_t seed, int64_t restart, double 
 // (A operand: lane l holds X^T[i][k], i = l % 16, k = l / 16; B operand: lane l
 // holds Y[k][j], j = l % 16; result: lane l, register v holds row 4 v + l / 16 of
 // column l % 16). Per-chunk tiles go to `partial`, summed in chunk order.
-typedef double v4d __attribute__((ext_vector_type(4)));
 static constexpr int TN_RC = 64;
 
 __global__ __launch_bounds__(TPB) void k_gemm_tn_mfma(int n, int p, int q, int rows_per_chunk,

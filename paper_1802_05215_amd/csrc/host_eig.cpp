@@ -305,23 +305,6 @@ void tridiag_eigvecs(int m, const double *d, const double *e, int nsel, const do
   }
 }
 
-// All eigenvalues (ascending, in w) of the symmetric m x m A (overwritten)
-// and the eigenvectors of those >= thr only: Householder reduction with the
-// reflectors kept, QR for the eigenvalues of the tridiagonal, inverse
-// iteration for the selected eigenvectors of the tridiagonal, and the
-// reflectors applied to those vectors. O(m^3) for the reduction but only
-// O(m^2 nsel) for the vectors. Vsel: m x nsel column-major, in the order of
-// w[m - nsel .. m - 1]; returns nsel.
-int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel) {
-  if (m <= 0) return -1;
-  std::vector<double> R((size_t)m * m, 0.0), betas(std::max(m, 1), 0.0);
-  std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
-  householder(m, A, d.data(), e.data(), R.data(), betas.data(), nullptr);
-  const int nsel = tridiag_eig_sel(m, d.data(), e.data(), w, thr, Vsel);
-  if (nsel > 0) apply_reflectors(m, R.data(), betas.data(), nsel, Vsel, m);
-  return nsel;
-}
-
 int tridiag_eig_sel(int m, const double *d, const double *e, double *w, double thr,
                     double *Vsel) {
   if (m <= 0) return -1;

@@ -41,11 +41,9 @@ int sym_eig(int m, double *A, double *w, double *V);
 // off-diagonal e (both overwritten); V as in sym_eig (identity or a prior
 // transformation, m x m) or null. O(m^2) without vectors.
 int tridiag_eig(int m, double *d, double *e, double *w, double *V);
-// All eigenvalues of the symmetric A (overwritten), ascending, and the
-// eigenvectors of those >= thr (Vsel, m x nsel, same order); returns nsel.
-int sym_eig_sel(int m, double *A, double *w, double thr, double *Vsel);
-// The same for a tridiagonal (d, e), not overwritten: QR for the eigenvalues,
-// inverse iteration for the selected eigenvectors.
+// All eigenvalues (ascending, in w) of the tridiagonal (d, e), not
+// overwritten, by QR, and the eigenvectors of those >= thr by inverse
+// iteration (Vsel, m x nsel, in the order of w[m - nsel .. m - 1]); returns nsel.
 int tridiag_eig_sel(int m, const double *d, const double *e, double *w, double thr,
                     double *Vsel);
 // The projected matrix after a thick restart (Section 2.3.2, arrowhead form):

@@ -1285,7 +1285,7 @@ int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int 
 
 namespace {
 
-// m Lanczos steps with full reorthogonalisation (two CGS passes) from the
+// m Lanczos steps with full reorthogonalisation (two CGS passes always) from the
 // start vector of stream (seed, block): alpha[i] = hs[2i], beta[i+1] =
 // hs[2i+1]. Stops early at an invariant subspace (beta <= 1e-12 of the
 // running scale); returns the dimension reached.

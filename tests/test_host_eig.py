@@ -26,7 +26,6 @@ def lib():
     L.t_tridiag_eig.argtypes = [C.c_int, dp, dp, dp, dp]
     L.t_tridiag_eigvecs.argtypes = [C.c_int, dp, dp, C.c_int, dp, dp]
     L.t_tridiag_eigvecs.restype = None
-    L.t_sym_eig_sel.argtypes = [C.c_int, dp, dp, C.c_double, dp]
     L.t_arrow_eig_sel.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_double, dp]
     return L
 
@@ -79,32 +78,30 @@ def test_tridiag_eig_and_inverse_iteration(lib, m, clusters):
     assert np.abs(Z.T @ Z - np.eye(len(sel))).max() <= 1e-10
 
 
-@pytest.mark.parametrize("m,kind", [(40, "random"), (300, "arrow"), (200, "clustered")])
-def test_sym_eig_selected_vectors(lib, m, kind):
-    """Eigenvalues of all, eigenvectors of the top ones only (thick-restart
-    T: an arrowhead block then a tridiagonal; clustered: repeated values)."""
+@pytest.mark.parametrize("m,kind", [(300, "arrow"), (200, "clustered")])
+def test_arrowhead_selected_vectors_large_and_clustered(lib, m, kind):
+    """Eigenvalues of all, eigenvectors of the top ones only, of a thick-restart
+    T (an arrowhead block then a tridiagonal; clustered: every Ritz value of the
+    block repeated, as for multiple eigenvalues) through the reduced form."""
     rng = np.random.default_rng(m)
-    if kind == "random":
-        M = rng.standard_normal((m, m))
-        M = (M + M.T) / 2
-    else:
-        l = m // 3
-        M = np.zeros((m, m))
-        th = np.sort(rng.uniform(0.5, 1.0, l))
-        if kind == "clustered":
-            th[1::2] = th[0::2][: len(th[1::2])]
-        M[np.arange(l), np.arange(l)] = th
-        M[:l, l] = M[l, :l] = rng.standard_normal(l) * 1e-3
-        M[np.arange(l, m), np.arange(l, m)] = rng.uniform(-1, 1, m - l)
-        off = rng.uniform(0.1, 0.5, m - l - 1)
-        M[np.arange(l, m - 1), np.arange(l + 1, m)] = off
-        M[np.arange(l + 1, m), np.arange(l, m - 1)] = off
+    l = m // 3
+    th = np.sort(rng.uniform(0.5, 1.0, l))
+    if kind == "clustered":
+        th[1::2] = th[0::2][: len(th[1::2])]
+    s = rng.standard_normal(l) * 1e-3
+    al = rng.uniform(-1, 1, m - l)
+    be = rng.uniform(0.1, 0.5, m - l - 1)
+    M = np.zeros((m, m))
+    M[np.arange(l), np.arange(l)] = th
+    M[:l, l] = M[l, :l] = s
+    M[np.arange(l, m), np.arange(l, m)] = al
+    M[np.arange(l, m - 1), np.arange(l + 1, m)] = be
+    M[np.arange(l + 1, m), np.arange(l, m - 1)] = be
     ref = np.linalg.eigvalsh(M)
     thr = float(np.quantile(ref, 0.7))
-    A = np.asfortranarray(M.copy())
     w = np.empty(m)
     V = np.zeros((m, m))
-    k = lib.t_sym_eig_sel(m, _p(A), _p(w), thr, _p(V))
+    k = lib.t_arrow_eig_sel(m, l, _p(th), _p(s), _p(al), _p(be), _p(w), thr, _p(V))
     assert k == int((ref >= thr).sum())
     assert np.abs(w - ref).max() <= 1e-12 * np.abs(ref).max()
     Z = V[:k].T

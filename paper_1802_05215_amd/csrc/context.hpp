@@ -225,6 +225,17 @@ inline double step_bytes(const evsl_csr_t *A, int nc, int s, int passes) {
   return ma + (double)passes * (double)A->n * nc * s;
 }
 
+// The block filter reads 16-bit column offsets from the row (half the index
+// bytes) when every |col - row| < 2^15; they are built into workspace slots
+// 26 and 27 (one pass over the matrix, synchronous). Ac.cd stays null for a
+// matrix of larger bandwidth.
+inline void attach_col_offsets(evsl_ctx_t ctx, const evsl_csr_t *A, evk::Csr &Ac) {
+  if (A->nnz <= 0) return;
+  int16_t *cd = (int16_t *)ws(ctx, 26, sizeof(int16_t) * (size_t)A->nnz);
+  int *flag = (int *)ws(ctx, 27, sizeof(int) * 4);
+  if (evk::make_col_offsets(ctx->stream, Ac, cd, flag)) Ac.cd = cd;
+}
+
 inline int pick_variant(evsl_ctx_t ctx) { return ctx->spmv_variant == 0 ? 3 : ctx->spmv_variant; }
 
 }  // namespace evc

@@ -331,11 +331,13 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
 // the row's entries from LDS and issues 8 gathers of VEC values at a time.
 // Element offsets are 32-bit when n * ld < 2^31, else (WIDE) 32 x 32 -> 64-bit
 // products; VEC > 1 needs nc and ld divisible by VEC and VEC-aligned base
-// pointers.
-template <typename T, int KIND, bool XCD, int VEC, bool WIDE>
+// pointers. With DELTA the column indices come as 16-bit offsets from the row
+// (cd), half the index bytes of a matrix whose bandwidth is below 2^15.
+template <typename T, int KIND, bool XCD, int VEC, bool WIDE, bool DELTA>
 __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_per_wg,
                                                       const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
+                                                      const int16_t *__restrict__ cd,
                                                       const T *__restrict__ va, T s1, T s0,
                                                       const T *__restrict__ W, const T *Wp, T *Wn,
                                                       T *Y, int64_t ld64,
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
   const bool staged = cnt <= CAP;
   if (staged) {
     for (int i = tid; i < cnt; i += TPB) {
-      s_ci[i] = ci[nz0 + i];
+      s_ci[i] = DELTA ? (int)cd[nz0 + i] : ci[nz0 + i];
       s_va[i] = va[nz0 + i];
     }
   }
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
     const T *wc = W + col;
     for (int rl = rsub; rl < nr; rl += R0) {
       const int kb = s_rp[rl] - nz0, ke = s_rp[rl + 1] - nz0;
+      const int row = r0 + rl;
       vt acc = (T)0;
       if (staged) {
         for (int k = kb; k < ke; k += 8) {
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const bool ok = k + u < ke;
-            const int c = ok ? s_ci[k + u] : 0;
+            const int c = ok ? (DELTA ? row + s_ci[k + u] : s_ci[k + u]) : row;
             a[u] = ok ? s_va[k + u] : (T)0;
             g[u] = *(const vt *)(wc + roff(c));
           }
@@ -416,9 +419,10 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
           for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
         }
       } else {
-        for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * *(const vt *)(wc + roff(ci[k]));
+        for (int k = kb + nz0; k < ke + nz0; ++k)
+          acc += va[k] * *(const vt *)(wc + roff(DELTA ? row + (int)cd[k] : ci[k]));
       }
-      const size_t e = roff(r0 + rl) + col;
+      const size_t e = roff(row) + col;
       const vt w = *(const vt *)(W + e);
       vt wn = s1 * acc + s0 * w;
       if (HAS_PREV) wn -= *(const vt *)(Wp + e);
@@ -496,25 +500,32 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
 #define EVK_BLK_ARGS                                                                          \
   grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, \
       jnext, Vd, partial
-#define EVK_LAUNCH_LDS(K, W)                                                                 \
+#define EVK_LDS_ARGS                                                                          \
+  grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, A.cd, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld,    \
+      coef, cld, jnext, Vd, partial
+#define EVK_LAUNCH_LDS(K, W, D)                                                              \
   do {                                                                                       \
     if (var == 3)                                                                            \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1, W>), EVK_BLK_ARGS);                 \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1, W, D>), EVK_LDS_ARGS);              \
     else if (vec == 4)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4, W>), EVK_BLK_ARGS);                  \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4, W, D>), EVK_LDS_ARGS);               \
     else if (vec == 2)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2, W>), EVK_BLK_ARGS);                  \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2, W, D>), EVK_LDS_ARGS);               \
     else                                                                                     \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1, W>), EVK_BLK_ARGS);                  \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1, W, D>), EVK_LDS_ARGS);               \
   } while (0)
 #define EVK_LAUNCH_BLK(K)                                                                    \
   do {                                                                                       \
     if (var == 1)                                                                            \
       hipLaunchKernelGGL((k_cheb_blk<T, K>), EVK_BLK_ARGS);                                  \
+    else if (wide && A.cd)                                                                   \
+      EVK_LAUNCH_LDS(K, true, true);                                                         \
     else if (wide)                                                                           \
-      EVK_LAUNCH_LDS(K, true);                                                               \
+      EVK_LAUNCH_LDS(K, true, false);                                                        \
+    else if (A.cd)                                                                           \
+      EVK_LAUNCH_LDS(K, false, true);                                                        \
     else                                                                                     \
-      EVK_LAUNCH_LDS(K, false);                                                              \
+      EVK_LAUNCH_LDS(K, false, false);                                                       \
   } while (0)
   switch (kind) {
     case STEP_PLAIN: EVK_LAUNCH_BLK(STEP_PLAIN); break;
@@ -526,6 +537,7 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
   }
 #undef EVK_LAUNCH_BLK
 #undef EVK_LAUNCH_LDS
+#undef EVK_LDS_ARGS
 #undef EVK_BLK_ARGS
 }
 
@@ -551,6 +563,37 @@ void fill_zero(hipStream_t s, int64_t count, T *p) {
 
 template void fill_zero<double>(hipStream_t, int64_t, double *);
 template void fill_zero<float>(hipStream_t, int64_t, float *);
+
+// cd[k] = col[k] - row(k); flag[0] = 1 when an offset does not fit 16 bits
+// (every writer stores the same value).
+__global__ __launch_bounds__(TPB) void k_col_offsets(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci, int16_t *cd,
+                                                     int *flag) {
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  if (r >= n) return;
+  bool bad = false;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) {
+    const int d = ci[k] - r;
+    if (d < -32768 || d > 32767) {
+      bad = true;
+      cd[k] = 0;
+    } else {
+      cd[k] = (int16_t)d;
+    }
+  }
+  if (bad) flag[0] = 1;
+}
+
+bool make_col_offsets(hipStream_t s, const Csr &A, int16_t *cd, int *flag) {
+  if (A.n <= 0) return false;
+  int h = 0;
+  if (hipMemcpyAsync(flag, &h, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return false;
+  hipLaunchKernelGGL(k_col_offsets, dim3((A.n + TPB - 1) / TPB), dim3(TPB), 0, s, A.n, A.rp, A.ci,
+                     cd, flag);
+  if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  return h == 0;
+}
 
 // ---------------------------------------------------------------- gather / scatter
 // blk (row-major, value type TB) <-> FP64 columns given by a device pointer array.

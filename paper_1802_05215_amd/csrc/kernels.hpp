@@ -12,7 +12,15 @@ struct Csr {
   const int *ci;
   const void *va;
   int dtype;  // 0 double, 1 float
+  // optional: col[k] - row(k) as 16-bit offsets (make_col_offsets); when set,
+  // the block filter reads these instead of ci
+  const int16_t *cd = nullptr;
 };
+
+// cd[k] = col[k] - row(k) for every nonzero; returns false (cd unusable) when
+// an offset does not fit 16 bits. `flag` is one device int of scratch.
+// Synchronous.
+bool make_col_offsets(hipStream_t s, const Csr &A, int16_t *cd, int *flag);
 
 // Step kinds of the three-term Chebyshev recurrence (eq:Cheb0) on
 // A-hat = (A - c I)/d:

@@ -1465,7 +1465,8 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
   const size_t es = prec == EVSL_F64 ? 8 : 4;
   void *Wa = ws(ctx, 11, es * (size_t)n * ldv);
   void *Wb = ws(ctx, 12, es * (size_t)n * ldv);
-  const evk::Csr Ac = to_csr(A);
+  evk::Csr Ac = to_csr(A);
+  if (!(ncols == 1 && ldv == 1)) attach_col_offsets(ctx, A, Ac);
   FilterTimer tm(ctx);
   double bytes = 0.0;
   int launches = 0;
@@ -1588,7 +1589,8 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   } hptrs;
   HC(ctx, hipHostMalloc(&hptrs.p, sizeof(double *) * 2 * (nslices + 1), hipHostMallocDefault));
   const double **hsrc = (const double **)hptrs.p;
-  const evk::Csr Ac = to_csr(A);
+  evk::Csr Ac = to_csr(A);
+  attach_col_offsets(ctx, A, Ac);
   const char *prog_env = std::getenv("EVSL_PROGRESS");
   const int progress = prog_env ? std::atoi(prog_env) : 0;
   long global_step = 0;

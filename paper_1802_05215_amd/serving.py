@@ -157,7 +157,9 @@ def footprint_parts(req: Request) -> Dict[str, int]:
                      + max(((n + 1023) // 1024) * (cols + 8),
                            ((n + 2047) // 2048) * (max(m, cap) + 2))
                      + 2 * (cols + 8) + 3 * m + 16 + (n + 255) // 256 + 2 + 10001)
-    batch = 8 * (3 * n * ns + ns * 10001 + 2 * (ns + 1)) + 8 * 2 * ld * m
+    # group blocks, coefficient table, pointer arrays, Ritz scratch, and the
+    # 16-bit column offsets of the block filter
+    batch = 8 * (3 * n * ns + ns * 10001 + 2 * (ns + 1)) + 8 * 2 * ld * m + 2 * nnz + 16
     vectors = 8 * n * cap * ns
     parts["library"] = ws + batch + ns * per_slice + vectors
     parts["results"] = vectors

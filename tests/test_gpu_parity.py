@@ -137,6 +137,40 @@ def test_filter_block_beyond_32bit_offsets(ctx, prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("permuted", [False, True])
+def test_filter_block_column_offsets_and_wide_bandwidth(ctx, permuted):
+    """The block filter reads 16-bit column offsets when the bandwidth allows
+    (a 2-D Laplacian, bandwidth 200) and the 32-bit indices otherwise (the same
+    matrix under a random symmetric permutation, bandwidth near n = 40,000);
+    both agree with the oracle on every column."""
+    A = I.laplacian(200, 2, pot_seed=3)
+    if permuted:
+        rng = np.random.default_rng(9)
+        P = rng.permutation(A.n)
+        inv = np.empty_like(P)
+        inv[P] = np.arange(A.n)
+        rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+        r2, c2 = inv[rows], inv[A.col]
+        order = np.lexsort((c2, r2))
+        r2, c2, v2 = r2[order], c2[order], A.val[order]
+        rp = np.zeros(A.n + 1, np.int64)
+        np.add.at(rp, r2 + 1, 1)
+        A = I.CSR(A.n, np.cumsum(rp).astype(np.int32), c2.astype(np.int32), v2.copy())
+        rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+        assert np.abs(A.col - rows).max() > 32767
+    Ad = ev.DeviceCsr.from_host(A)
+    p = _pol([1.0, 1.2, 0.0, 9.0])
+    rng = np.random.default_rng(10)
+    Vh = rng.standard_normal((A.n, 6))
+    V = _dev(Vh)
+    Y = torch.empty_like(V)
+    ev.evsl_filter_apply(ctx, Ad, [p], [0] * 6, V, Y)
+    torch.cuda.synchronize()
+    ref = oracle.filter_apply(A, p.cc, p.dd, p.coef, Vh)
+    err = np.linalg.norm(Y.cpu().numpy() - ref, axis=0) / np.linalg.norm(Vh, axis=0)
+    assert err.max() <= 1e-11
+
+
 def test_filter_dense_rows_fall_back(ctx):
     """A matrix whose rows exceed the LDS stage (a dense 300 x 300 block)."""
     rng = np.random.default_rng(2)

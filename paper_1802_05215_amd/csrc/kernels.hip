@@ -142,11 +142,13 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds(int n, const int *__restri
 
 // LDS-staged CSR stream with the nonzero loop unrolled by 8: the column
 // indices and values of 8 entries come from LDS, their 8 gathers are issued
-// together (padding entries read element 0 and are multiplied by 0), then
-// accumulated in index order. XCD=true remaps workgroups per XCD.
-template <typename T, int KIND, bool XCD>
+// together (padding entries read the row's own element and are multiplied by
+// 0), then accumulated in index order. XCD=true remaps workgroups per XCD.
+// With DELTA the columns come as 16-bit offsets from the row (cd).
+template <typename T, int KIND, bool XCD, bool DELTA>
 __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restrict__ rp,
                                                        const int *__restrict__ ci,
+                                                       const int16_t *__restrict__ cd,
                                                        const T *__restrict__ va, T s1, T s0,
                                                        const T *__restrict__ W, const T *Wp, T *Wn,
                                                        T *Y, int64_t ld,
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
   const bool staged = cnt <= CAP;
   if (staged) {
     for (int i = threadIdx.x; i < cnt; i += TPB) {
-      s_ci[i] = ci[nz0 + i];
+      s_ci[i] = DELTA ? (int)cd[nz0 + i] : ci[nz0 + i];
       s_va[i] = va[nz0 + i];
     }
   }
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const bool ok = k + u < ke;
-        const int c = ok ? s_ci[k + u] : 0;
+        const int c = ok ? (DELTA ? r + s_ci[k + u] : s_ci[k + u]) : r;
         a[u] = ok ? s_va[k + u] : (T)0;
         g[u] = w[c];
       }
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_vec_lds8(int n, const int *__restr
       for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
     }
   } else {
-    for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * w[ci[k]];
+    for (int k = kb + nz0; k < ke + nz0; ++k) acc += va[k] * w[DELTA ? r + (int)cd[k] : ci[k]];
   }
   const T wr = w[r];
   T wn = s1 * acc + s0 * wr;
@@ -221,21 +223,32 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
   hipLaunchKernelGGL((KERN<T, K>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, \
                      Wp, Wn, Y, ld, coef, cld, jnext, Vd)
   if (variant == 3 || variant == 4) {
-    if (variant == 3) {
-      switch (kind) {
-        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        case STEP_CLEN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_CLEN, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, true>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+#define EVK_LAUNCH_LDS8(K, X, D)                                                                \
+  hipLaunchKernelGGL((k_cheb_vec_lds8<T, K, X, D>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, A.cd, \
+                     va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd)
+#define EVK_LAUNCH_LDS8_K(X, D)                                      \
+  switch (kind) {                                                    \
+    case STEP_PLAIN: EVK_LAUNCH_LDS8(STEP_PLAIN, X, D); break;       \
+    case STEP_FIRST: EVK_LAUNCH_LDS8(STEP_FIRST, X, D); break;       \
+    case STEP_CLEN: EVK_LAUNCH_LDS8(STEP_CLEN, X, D); break;         \
+    default: EVK_LAUNCH_LDS8(STEP_NEXT, X, D); break;                \
+  }
+    const bool xcd = variant == 3;
+    if (A.cd) {
+      if (xcd) {
+        EVK_LAUNCH_LDS8_K(true, true)
+      } else {
+        EVK_LAUNCH_LDS8_K(false, true)
       }
     } else {
-      switch (kind) {
-        case STEP_PLAIN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_PLAIN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        case STEP_FIRST: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_FIRST, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        case STEP_CLEN: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_CLEN, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
-        default: hipLaunchKernelGGL((k_cheb_vec_lds8<T, STEP_NEXT, false>), grid, dim3(TPB), 0, s, A.n, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, jnext, Vd); break;
+      if (xcd) {
+        EVK_LAUNCH_LDS8_K(true, false)
+      } else {
+        EVK_LAUNCH_LDS8_K(false, false)
       }
     }
+#undef EVK_LAUNCH_LDS8_K
+#undef EVK_LAUNCH_LDS8
   } else if (variant == 2) {
     switch (kind) {
       case STEP_PLAIN: EVK_LAUNCH_VEC(k_cheb_vec_lds, STEP_PLAIN); break;

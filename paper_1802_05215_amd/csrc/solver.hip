@@ -117,6 +117,8 @@ struct Slice {
   // graph form of the single-vector filter: the deg launches read a fixed
   // input (qin, or q32 in FP32) so one captured graph serves every step
   double *qin = nullptr;
+  // 16-bit column offsets of A (context workspace) or null: see attach_col_offsets
+  const int16_t *cd = nullptr;
   hipGraph_t fg = nullptr;
   hipGraphExec_t fgx = nullptr;
   int fg_var = -1;
@@ -313,6 +315,7 @@ struct Slice {
     evk::Csr c = to_csr(A);
     c.va = val32;
     c.dtype = EVSL_F32;
+    c.cd = cd;
     return c;
   }
 
@@ -413,7 +416,8 @@ struct Slice {
 
   // z = rho(A-hat) q in FP64
   void recurrence_f64(hipStream_t s, int var, const double *q) {
-    const evk::Csr Ac = to_csr(A);
+    evk::Csr Ac = to_csr(A);
+    Ac.cd = cd;
     if (single_clenshaw()) {
       clenshaw_vec<double>(s, Ac, var, q, w0, w1, z);
       return;
@@ -1246,7 +1250,8 @@ int evsl_kpm_dos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4], int 
   double *part = (double *)ws(ctx, 3, sizeof(double) * ((size_t)nw * (degree + 1) + nwd + 8));
   double *mom_dev = (double *)ws(ctx, 4, sizeof(double) * (degree + 2));
   hipStream_t s = ctx->stream;
-  const evk::Csr Ac = to_csr(A);
+  evk::Csr Ac = to_csr(A);
+  attach_col_offsets(ctx, A, Ac);
   // launches may write fewer partials than the bound nw (wider vector slots)
   HC(ctx, hipMemsetAsync(part, 0, sizeof(double) * (size_t)nw * (degree + 1), s));
   evk::rademacher(s, n, nvec, seed, V);
@@ -1466,7 +1471,7 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
   void *Wa = ws(ctx, 11, es * (size_t)n * ldv);
   void *Wb = ws(ctx, 12, es * (size_t)n * ldv);
   evk::Csr Ac = to_csr(A);
-  if (!(ncols == 1 && ldv == 1)) attach_col_offsets(ctx, A, Ac);
+  attach_col_offsets(ctx, A, Ac);
   FilterTimer tm(ctx);
   double bytes = 0.0;
   int launches = 0;
@@ -1533,6 +1538,11 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
   const double t0 = now_s();
   Slice sl;
   sl.setup(ctx, A, intv, pol, opt);
+  {
+    evk::Csr Ac = to_csr(A);
+    attach_col_offsets(ctx, A, Ac);
+    sl.cd = Ac.cd;
+  }
   while (!sl.done) {
     sl.filter_single();
     sl.orth_and_queue();
@@ -1591,6 +1601,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   const double **hsrc = (const double **)hptrs.p;
   evk::Csr Ac = to_csr(A);
   attach_col_offsets(ctx, A, Ac);
+  for (auto &x : sl) x.cd = Ac.cd;
   const char *prog_env = std::getenv("EVSL_PROGRESS");
   const int progress = prog_env ? std::atoi(prog_env) : 0;
   long global_step = 0;

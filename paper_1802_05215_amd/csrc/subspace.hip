@@ -315,7 +315,8 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
   } hptrs;
   HC(ctx, hipHostMalloc(&hptrs.p, sizeof(double *) * 2 * (size_t)btot, hipHostMallocDefault));
   const double **hp = (const double **)hptrs.p;
-  const evk::Csr Ac = to_csr(A);
+  evk::Csr Ac = to_csr(A);
+  attach_col_offsets(ctx, A, Ac);
   std::vector<int> act;
   std::vector<double> tab;
   std::vector<int> ncs(kmax + 2);
@@ -353,19 +354,23 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
     HC(ctx, hipMemcpyAsync(ptrs, hp, sizeof(double *) * 2 * nc, hipMemcpyHostToDevice, s));
     const double tf0 = now_s();
     FilterTimer tm(ctx);
+    // W = p(A-hat) V by Clenshaw's recurrence (as in the Lanczos batch): B_k
+    // over B_{k+2}, four passes per degree step; columns join as k reaches
+    // their slice's degree (slices in non-increasing degree)
     evk::gather_cols<double>(s, n, nc, (const double *const *)ptrs, X0, ldb);
-    evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, ldb,
-                          ncs[1], ctab, km + 1, 1, nullptr, nullptr);
-    double bytes = step_bytes(A, ncs[1], 8, 3);
-    double *wprev = X0, *wcur = X1;
-    for (int j = 1; j < km; ++j) {
-      evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
-                            Yb, ldb, ncs[j + 1], ctab, km + 1, j + 1, nullptr, nullptr);
-      bytes += step_bytes(A, ncs[j + 1], 8, 5);
-      std::swap(wprev, wcur);
+    evk::fill_zero<double>(s, (int64_t)n * ldb, X1);
+    evk::fill_zero<double>(s, (int64_t)n * ldb, Yb);
+    double bytes = 2.0 * (double)n * (double)ldb * 8.0;
+    double *bk1 = X1, *bk2 = Yb;
+    for (int k = km; k >= 0; --k) {
+      const double sc = k > 0 ? 2.0 : 1.0;
+      evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
+                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr);
+      bytes += step_bytes(A, ncs[k], 8, 4);
+      std::swap(bk1, bk2);
     }
-    evk::scatter_cols<double>(s, n, nc, Yb, ldb, (double *const *)(ptrs + nc));
-    tm.stop(km, bytes);
+    evk::scatter_cols<double>(s, n, nc, bk1, ldb, (double *const *)(ptrs + nc));
+    tm.stop(km + 1, bytes);
     HC(ctx, hipStreamSynchronize(s));
     const double tf = now_s() - tf0;
     for (int q : act) {

@@ -144,7 +144,7 @@ def footprint_parts(req: Request) -> Dict[str, int]:
               + max(82, _blk_partials(n, nv) * (K + 1) + (n * nv + 2047) // 2048 + 8)
               + max(K + 2, 82) + 256)
     if req.kind == "dos":
-        parts["library"] = ws
+        parts["library"] = ws + 2 * nnz + 16   # with the 16-bit column offsets
         parts["results"] = 0
         return parts
     ns = req.nslices

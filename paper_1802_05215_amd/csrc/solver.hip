@@ -796,7 +796,7 @@ struct Slice {
       nmv += P * dp;
       Yq = Sm + (int64_t)P * ld;
       evk::scatter_cols<double>(s, n, P, Yb, P, (double *const *)(pp + P));
-      // Round 0: S = [U, Z] with Z an orthonormal basis of (I - U U^T) p(A) U
+      // First polish round: S = [U, Z] with Z an orthonormal basis of (I - U U^T) p(A) U
       // (directions negligible against |p(A) U| dropped: they carry only
       // rounding). Later rounds: S = an orthonormal basis of p(A) U alone
       // (filtered subspace iteration): once U is accurate, the projected-out

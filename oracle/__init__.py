@@ -95,6 +95,7 @@ def _setup(L):
     L.or_filtered_lanczos_gen.argtypes = [C.c_int64, _ip, _ip, _dp, _ip, _ip, _dp, _dp, C.c_int, _dp,
                                           C.c_double, C.POINTER(LanOpts), _dp, _dp, _dp,
                                           C.POINTER(LanStats)]
+    L.or_filtered_lanczos_gen_tr.argtypes = L.or_filtered_lanczos_gen.argtypes
     L.or_lanczos_dos.argtypes = [C.c_int64, _ip, _ip, _dp, C.c_int, C.c_int, C.c_uint64, _dp, _dp,
                                  _ip]
     L.or_lanczos_count.argtypes = [_dp, _dp, _ip, C.c_int, C.c_int, C.c_int64, C.c_double,
@@ -407,4 +408,36 @@ def filtered_lanczos_gen(A, B, intv, pol, m=None, ncycle=30, tol=1e-10, seed=2, 
         raise ValueError("filtered_lanczos_gen: invalid arguments")
     k = st.nev
     stats = dict(nev=k, niter=st.niter, nmv=st.nmv, status=st.status)
+    return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats
+
+
+def filtered_lanczos_gen_tr(A, B, intv, pol, m=None, max_its=None, ncycle=30, tol=1e-10, seed=2,
+                            nev_cap=None, nev_est=None):
+    """Filtered thick-restart Lanczos for the pencil (A, B) (Algorithm
+    alg:FiltLanTR in the B-inner product). Returns (lam, Y (n x nev,
+    B-orthonormal), res, stats)."""
+    if nev_est is None:
+        nev_est = 50
+    if m is None:
+        m = max(3 * int(nev_est) + 30, 60)
+    if max_its is None:
+        max_its = max(20 * m, 2000)
+    if nev_cap is None:
+        nev_cap = max(4 * int(nev_est) + 40, 100)
+    n = A.n
+    ra, ca, va = _csr(A)
+    rb, cb, vb = _csr(B)
+    iv = _f64(intv)
+    coef = _f64(pol["coef"])
+    lam, res = np.empty(nev_cap), np.empty(nev_cap)
+    Y = np.empty((nev_cap, n))
+    opts = LanOpts(m, max_its, ncycle, tol, seed, nev_cap)
+    st = LanStats()
+    rc = lib().or_filtered_lanczos_gen_tr(n, _i(ra), _i(ca), _d(va), _i(rb), _i(cb), _d(vb),
+                                          _d(iv), len(coef) - 1, _d(coef), pol["bar"],
+                                          C.byref(opts), _d(lam), _d(res), _d(Y), C.byref(st))
+    if rc != 0:
+        raise ValueError("filtered_lanczos_gen_tr: invalid arguments")
+    k = st.nev
+    stats = dict(nev=k, niter=st.niter, nmv=st.nmv, nrestart=st.nrestart, status=st.status)
     return lam[:k].copy(), Y[:k].T.copy(), res[:k].copy(), stats

@@ -1295,3 +1295,250 @@ int or_filtered_lanczos_gen(int64_t n, const int32_t *rp, const int32_t *ci, con
   free(h);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Generalized problems, thick-restart form: Algorithm alg:FiltLanTR carried
+ * out in the B-inner product with the two bases of Algorithm alg:LanAB (W
+ * B-orthonormal, Z = B W) and the filtered step of eq:polyapp1. The locked
+ * vectors U are B-orthonormal and kept with B U; in the z-representation the
+ * deflation subtracts B U (U^T z) and the full reorthogonalisation (two
+ * classical Gram-Schmidt passes, as in the non-restart form) subtracts
+ * B U (U^T z) and Z (W^T z). Ritz vectors of T are u = W y with B u = Z y; a
+ * candidate is accepted when lambda = u^T A u / u^T B u lies in the slice and
+ * ||A u - lambda B u|| / (||B u|| max(|lambda_min|, |lambda_max|)) <= tol.
+ * Every other reading (candidates, arrowhead T, early-restart sums, extra
+ * restart, kept Ritz vectors) is that of or_filtered_lanczos. Y holds the
+ * B-normalised locked vectors. */
+static void gen_fresh(int64_t n, const int32_t *rpb, const int32_t *cib, const double *vb,
+                      uint64_t seed, int idx, const double *U, const double *BU, int nlock,
+                      const double *W, const double *Z, int k, double *w, double *z, double *nrm) {
+  or_lanczos_start(seed, n, idx, w);
+  or_spmv(n, rpb, cib, vb, w, z);
+  const double n0 = sqrt(fmax(dot(n, w, z), 0.0));
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < nlock; ++j) {
+      const double hj = dot(n, BU + (size_t)j * n, w);
+      for (int64_t r = 0; r < n; ++r) w[r] -= hj * U[(size_t)j * n + r];
+    }
+    for (int j = 0; j < k; ++j) {
+      const double hj = dot(n, Z + (size_t)j * n, w);
+      for (int64_t r = 0; r < n; ++r) w[r] -= hj * W[(size_t)j * n + r];
+    }
+  }
+  or_spmv(n, rpb, cib, vb, w, z);
+  const double nb = sqrt(fmax(dot(n, w, z), 0.0));
+  *nrm = nb > 1e-10 * n0 ? nb : 0.0;
+  if (*nrm > 0.0)
+    for (int64_t r = 0; r < n; ++r) { w[r] /= nb; z[r] /= nb; }
+}
+
+int or_filtered_lanczos_gen_tr(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *rpb, const int32_t *cib, const double *vb,
+                               const double intv[4], int deg, const double *coef, double bar,
+                               const or_lan_opts *opt, double *lam, double *res, double *Y,
+                               or_lan_stats *st) {
+  memset(st, 0, sizeof(*st));
+  double tlo = intv[0], thi = intv[1];
+  const double lmin = intv[2], lmax = intv[3];
+  /* a slice that reaches a bound of the spectrum owns every eigenvalue
+   * beyond it */
+  if (tlo <= lmin) tlo = -INFINITY;
+  if (thi >= lmax) thi = INFINITY;
+  const double normA = fabs(lmin) > fabs(lmax) ? fabs(lmin) : fabs(lmax);
+  const double cc = 0.5 * (lmax + lmin), dd = 0.5 * (lmax - lmin);
+  int m = opt->m;
+  if (m > n - 1) m = (int)(n - 1);
+  if (m < 2 || deg < 1 || opt->ncycle < 1) return -1;
+  const int M1 = m + 1;
+  double *W = (double *)calloc((size_t)n * M1, sizeof(double));
+  double *Z = (double *)calloc((size_t)n * M1, sizeof(double));
+  double *BU = (double *)calloc((size_t)n * (opt->nev_cap > 0 ? opt->nev_cap : 1), sizeof(double));
+  double *TRw = (double *)malloc(sizeof(double) * (size_t)n * m);
+  double *TRz = (double *)malloc(sizeof(double) * (size_t)n * m);
+  double *T = (double *)calloc((size_t)M1 * M1, sizeof(double));
+  double *Tw = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *w = (double *)malloc(sizeof(double) * m);
+  double *Yv = (double *)malloc(sizeof(double) * (size_t)m * m);
+  double *z = (double *)malloc(sizeof(double) * n), *zw = (double *)malloc(sizeof(double) * n);
+  double *u = (double *)malloc(sizeof(double) * n), *bu = (double *)malloc(sizeof(double) * n);
+  double *au = (double *)malloc(sizeof(double) * n);
+  double *h = (double *)malloc(sizeof(double) * (opt->nev_cap + m + 2));
+  double *thTR = (double *)malloc(sizeof(double) * m), *sTR = (double *)malloc(sizeof(double) * m);
+#define TT(i, j) T[(i) + (size_t)(j) * M1]
+  int nlock = 0, l = 0, its = 0, nmv = 0, nrand = 0, nocand = 0, nrestart = 0, status = 0;
+  double nz;
+  gen_fresh(n, rpb, cib, vb, opt->seed, nrand++, Y, BU, 0, W, Z, 0, W, Z, &nz);
+  double t_old = NAN, t_new = NAN;
+  while (its <= opt->max_its) {
+    int dim = m, next_ok = 1;
+    for (int i = l; i < m; ++i) {
+      its++;
+      double *wi = W + (size_t)i * n, *zi = Z + (size_t)i * n;
+      /* eq:polyapp1: z = rho(A-hat B^(-1)) z_i */
+      gen_filter(n, rp, ci, va, rpb, cib, vb, cc, dd, deg, coef, zi, z);
+      nmv += deg;
+      /* deflation: z <- z - B U (U^T z) */
+      for (int j = 0; j < nlock; ++j) h[j] = dot(n, Y + (size_t)j * n, z);
+      for (int j = 0; j < nlock; ++j)
+        for (int64_t r = 0; r < n; ++r) z[r] -= h[j] * BU[(size_t)j * n + r];
+      const double alpha = dot(n, z, wi);
+      if (i == l && l > 0) { /* special TR step: couplings to the TR vectors */
+        for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r];
+        for (int j = 0; j < l; ++j) {
+          const double sj = TT(j, l);
+          for (int64_t r = 0; r < n; ++r) z[r] -= sj * Z[(size_t)j * n + r];
+        }
+      } else if (i > l) {
+        const double bi = TT(i - 1, i);
+        for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r] + bi * zi[r - n];
+      } else {
+        for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r];
+      }
+      TT(i, i) = alpha;
+      /* full reorthogonalisation against [U, w_1..w_i] (two passes) */
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < nlock; ++j) h[j] = dot(n, Y + (size_t)j * n, z);
+        for (int j = 0; j <= i; ++j) h[nlock + j] = dot(n, W + (size_t)j * n, z);
+        for (int j = 0; j < nlock; ++j)
+          for (int64_t r = 0; r < n; ++r) z[r] -= h[j] * BU[(size_t)j * n + r];
+        for (int j = 0; j <= i; ++j)
+          for (int64_t r = 0; r < n; ++r) z[r] -= h[nlock + j] * Z[(size_t)j * n + r];
+      }
+      double *wn = W + (size_t)(i + 1) * n, *zn = Z + (size_t)(i + 1) * n;
+      or_cg_solve(n, rpb, cib, vb, z, wn);
+      const double beta = sqrt(fmax(dot(n, wn, z), 0.0));
+      if (beta <= 1e-12) {
+        /* invariant subspace of the filtered operator: new direction, coupling 0 */
+        gen_fresh(n, rpb, cib, vb, opt->seed, nrand++, Y, BU, nlock, W, Z, i + 1, wn, zn, &nz);
+        TT(i, i + 1) = TT(i + 1, i) = 0.0;
+        if (nz == 0.0) { dim = i + 1; next_ok = 0; break; }
+      } else {
+        for (int64_t r = 0; r < n; ++r) { wn[r] /= beta; zn[r] = z[r] / beta; }
+        TT(i, i + 1) = TT(i + 1, i) = beta;
+      }
+      if (((i + 1) - l) % opt->ncycle == 0) {
+        const int k = i + 1;
+        for (int jj = 0; jj < k; ++jj)
+          for (int ii = 0; ii < k; ++ii) Tw[ii + (size_t)jj * k] = TT(ii, jj);
+        or_jacobi_eig(k, Tw, w, Yv);
+        t_old = t_new;
+        t_new = 0.0;
+        for (int jj = 0; jj < k; ++jj)
+          if (w[jj] >= bar) t_new += w[jj];
+        if (fabs(t_new - t_old) < 1e-10 * (fabs(t_new) > 1.0 ? fabs(t_new) : 1.0)) {
+          dim = k;
+          break;
+        }
+      }
+      if (its > opt->max_its) { dim = i + 1; break; }
+    }
+    /* Rayleigh-Ritz on T_dim */
+    nrestart++;
+    for (int jj = 0; jj < dim; ++jj)
+      for (int ii = 0; ii < dim; ++ii) Tw[ii + (size_t)jj * dim] = TT(ii, jj);
+    or_jacobi_eig(dim, Tw, w, Yv);
+    const double beta_last = next_ok ? TT(dim - 1, dim) : 0.0;
+    const int cap_tr = m - (opt->ncycle > 10 ? opt->ncycle : 10) > 0
+                           ? m - (opt->ncycle > 10 ? opt->ncycle : 10) : 1;
+    int lnew = 0, naccept = 0;
+    for (int jj = dim - 1; jj >= 0 && w[jj] >= bar; --jj) {
+      const double *y = Yv + (size_t)jj * dim;
+      for (int64_t r = 0; r < n; ++r) {
+        double s = 0.0, sb = 0.0;
+        for (int p = 0; p < dim; ++p) {
+          s += W[(size_t)p * n + r] * y[p];
+          sb += Z[(size_t)p * n + r] * y[p];
+        }
+        u[r] = s;
+        bu[r] = sb;
+      }
+      or_spmv(n, rp, ci, va, u, au);
+      nmv++;
+      const double ubu = dot(n, u, bu);
+      const double lam_j = dot(n, u, au) / ubu;
+      if (lam_j < tlo || lam_j > thi) continue; /* outside the slice: ignored */
+      naccept++;
+      double rr = 0.0;
+      for (int64_t r = 0; r < n; ++r) {
+        const double e = au[r] - lam_j * bu[r];
+        rr += e * e;
+      }
+      rr = sqrt(rr) / (nrm2(n, bu) * normA);
+      if (rr <= opt->tol) {
+        if (nlock >= opt->nev_cap) { status = 2; goto done; }
+        const double nb = sqrt(ubu);
+        for (int64_t r = 0; r < n; ++r) {
+          Y[(size_t)nlock * n + r] = u[r] / nb;
+          BU[(size_t)nlock * n + r] = bu[r] / nb;
+        }
+        lam[nlock] = lam_j;
+        res[nlock] = rr;
+        nlock++;
+      } else if (lnew < cap_tr) {
+        memcpy(TRw + (size_t)lnew * n, u, sizeof(double) * n);
+        memcpy(TRz + (size_t)lnew * n, bu, sizeof(double) * n);
+        thTR[lnew] = w[jj];
+        sTR[lnew] = beta_last * y[dim - 1];
+        lnew++;
+      }
+    }
+    if (naccept == 0) {
+      nocand++;
+      if (nocand >= 2) break;
+    } else {
+      nocand = 0;
+    }
+    memset(T, 0, sizeof(double) * (size_t)M1 * M1);
+    if (naccept == 0) {
+      /* extra restart from a fresh random vector B-orthogonal to the locked set */
+      gen_fresh(n, rpb, cib, vb, opt->seed, nrand++, Y, BU, nlock, W, Z, 0, zw, z, &nz);
+      if (nz == 0.0) break;
+      memcpy(W, zw, sizeof(double) * n);
+      memcpy(Z, z, sizeof(double) * n);
+      l = 0;
+    } else {
+      if (next_ok) {
+        memcpy(zw, W + (size_t)dim * n, sizeof(double) * n);
+        memcpy(z, Z + (size_t)dim * n, sizeof(double) * n);
+      }
+      memcpy(W, TRw, sizeof(double) * (size_t)n * lnew);
+      memcpy(Z, TRz, sizeof(double) * (size_t)n * lnew);
+      if (!next_ok) {
+        gen_fresh(n, rpb, cib, vb, opt->seed, nrand++, Y, BU, nlock, W, Z, lnew, zw, z, &nz);
+        if (nz == 0.0) break;
+        for (int j = 0; j < lnew; ++j) sTR[j] = 0.0;
+      }
+      memcpy(W + (size_t)lnew * n, zw, sizeof(double) * n);
+      memcpy(Z + (size_t)lnew * n, z, sizeof(double) * n);
+      for (int j = 0; j < lnew; ++j) {
+        TT(j, j) = thTR[j];
+        TT(j, lnew) = sTR[j];
+        TT(lnew, j) = sTR[j];
+      }
+      l = lnew;
+    }
+  }
+  if (its > opt->max_its) status = 1;
+done:
+  for (int i = 0; i < nlock - 1; ++i) {
+    int mi = i;
+    for (int j = i + 1; j < nlock; ++j)
+      if (lam[j] < lam[mi]) mi = j;
+    if (mi != i) {
+      double t = lam[i]; lam[i] = lam[mi]; lam[mi] = t;
+      t = res[i]; res[i] = res[mi]; res[mi] = t;
+      memcpy(u, Y + (size_t)i * n, sizeof(double) * n);
+      memcpy(Y + (size_t)i * n, Y + (size_t)mi * n, sizeof(double) * n);
+      memcpy(Y + (size_t)mi * n, u, sizeof(double) * n);
+    }
+  }
+#undef TT
+  st->nev = nlock;
+  st->niter = its;
+  st->nmv = nmv;
+  st->nrestart = nrestart;
+  st->status = status;
+  free(W); free(Z); free(BU); free(TRw); free(TRz); free(T); free(Tw); free(w); free(Yv);
+  free(z); free(zw); free(u); free(bu); free(au); free(h); free(thTR); free(sTR);
+  return 0;
+}

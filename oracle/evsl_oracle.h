@@ -180,6 +180,15 @@ int or_filtered_lanczos_gen(int64_t n, const int32_t *rp, const int32_t *ci, con
                             const or_lan_opts *opt, double *lam, double *res, double *Y,
                             or_lan_stats *st);
 
+/* The thick-restart form of Algorithm alg:FiltLanTR for the pencil, in the
+ * B-inner product with the bases of Algorithm alg:LanAB; locked vectors
+ * B-orthonormal (Y), every reading as or_filtered_lanczos. */
+int or_filtered_lanczos_gen_tr(int64_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *rpb, const int32_t *cib, const double *vb,
+                               const double intv[4], int deg, const double *coef, double bar,
+                               const or_lan_opts *opt, double *lam, double *res, double *Y,
+                               or_lan_stats *st);
+
 typedef struct {
   int block;      /* subspace dimension b */
   int max_its;    /* cap on iterations */

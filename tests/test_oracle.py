@@ -641,6 +641,29 @@ def test_filtered_lanczos_gen_fe_pencil_closed_form(ab):
     assert np.linalg.norm(R, axis=0).max() <= 1e-9 * ex[-1]
 
 
+@pytest.mark.parametrize("ab", [(0.5, 1.2), (2.0, 3.0)])
+def test_filtered_lanczos_gen_thick_restart_fe_pencil_closed_form(ab):
+    """The thick-restart form for the pencil finds every eigenvalue of the
+    slice, the double ones (lambda = mu_i + mu_j = mu_j + mu_i) included, with
+    B-orthonormal vectors."""
+    A, B = I.fe_pencil(16)
+    ex = _fe_eigs(16)
+    want = ex[(ex >= ab[0]) & (ex <= ab[1])]
+    assert np.any(np.diff(want) < 1e-12)            # the slice holds double eigenvalues
+    lo, hi = oracle.lanczos_bounds_gen(A, B, 80, 3)
+    intv = [ab[0], ab[1], lo, hi]
+    p = oracle.find_pol(intv, damping=oracle.DAMP_JACKSON)
+    lam, Y, res, st = oracle.filtered_lanczos_gen_tr(A, B, intv, p, tol=1e-10,
+                                                     nev_est=len(want))
+    assert st["status"] == 0 and len(lam) == len(want)
+    assert np.abs(lam - want).max() <= 1e-11 * ex[-1]
+    assert res.max() <= 1e-10
+    Db = B.to_dense()
+    assert np.abs(Y.T @ Db @ Y - np.eye(len(lam))).max() <= 1e-10
+    R = A.to_dense() @ Y - Db @ Y * lam
+    assert np.linalg.norm(R, axis=0).max() <= 1e-9 * ex[-1]
+
+
 def test_paper_counts_from_closed_form():
     for r in GOLD["lap_problems"]["rows"]:
         if r["n"] > 600000:

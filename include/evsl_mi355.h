@@ -289,15 +289,17 @@ int evsl_lspol(int kind, double lo, double hi, int deg, double *coef);
 int evsl_spectrum_bounds_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_csr_t *B,
                              const double bbounds[2], int bdeg, int nsteps, uint64_t seed,
                              double *lmin, double *lmax);
-/* Filtered non-restart Lanczos for (A, B) on one slice: Algorithm alg:LanAB
- * applied to (B rho(B^-1 A-hat), B), its product step as eq:polyapp1 (per degree step one
- * solve with B and one product with A), full reorthogonalisation, the settled
- * sum test of EVSL_LAN_NR; intv = {t_i, t_{i+1}, lambda_min, lambda_max} of the
- * pencil and pol from evsl_cheb_coeffs on it. opt as for the non-restart form
- * (method EVSL_LAN_TR and prec EVSL_F32: EVSL_ENOTIMPL). Returns the Ritz pairs
- * in the slice with ||A y - lambda B y|| / (||B y|| max(|lambda_min|,
- * |lambda_max|)) <= tol; Y is B-orthonormal. out->nrestart counts the solves
- * with B. Synchronous. */
+/* Filtered Lanczos for (A, B) on one slice: Algorithm alg:LanAB applied to
+ * (B rho(B^-1 A-hat), B), its product step as eq:polyapp1 (per degree step one
+ * solve with B and one product with A), full reorthogonalisation. With
+ * opt->method = EVSL_LAN_NR (or opt NULL) the non-restart form and its settled
+ * sum test; with EVSL_LAN_TR the thick-restart form of Algorithm
+ * alg:FiltLanTR in the B-inner product (locked vectors B-orthonormal, the same
+ * sizes and readings as evsl_filtered_lanczos). intv = {t_i, t_{i+1},
+ * lambda_min, lambda_max} of the pencil and pol from evsl_cheb_coeffs on it;
+ * prec EVSL_F32: EVSL_ENOTIMPL. Returns the Ritz pairs in the slice with
+ * ||A y - lambda B y|| / (||B y|| max(|lambda_min|, |lambda_max|)) <= tol; Y is
+ * B-orthonormal. out->nrestart counts the solves with B. Synchronous. */
 int evsl_filtered_lanczos_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_csr_t *B,
                               const double bbounds[2], int bdeg, const double intv[4],
                               const evsl_pol_t *pol, const evsl_lan_opts_t *opt,

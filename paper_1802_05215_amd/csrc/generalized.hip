@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "context.hpp"
@@ -110,8 +111,10 @@ struct GenSolver {
   }
   hipStream_t st() const { return ctx->stream; }
 
+  // ncols_max: the most columns a Gram-Schmidt product spans (the basis, or
+  // the locked block of the thick-restart form when that is larger)
   void setup(evsl_ctx_t c, const evsl_csr_t *Am, const evsl_csr_t *Bm, const double bb[2],
-             int bdeg, int msteps) {
+             int bdeg, int msteps, int ncols_max = 0) {
     ctx = c;
     A = Am;
     B = Bm;
@@ -130,7 +133,8 @@ struct GenSolver {
     W = alloc((size_t)ld * (m + 1));
     Z = alloc((size_t)ld * (m + 1));
     for (double **p : {&zb, &wb, &u, &t, &f1, &f2, &s1, &s2}) *p = alloc(ld);
-    partial = alloc(std::max(evk::gemv_partials(n, m + 2), evk::dot_partials(n, 2)));
+    partial = alloc(std::max(evk::gemv_partials(n, std::max(m + 2, ncols_max)),
+                             evk::dot_partials(n, 2)));
     h1 = alloc(m + 2);
     h2 = alloc(m + 2);
     nrm2 = alloc(8);
@@ -252,6 +256,288 @@ struct GenSolver {
   }
 };
 
+// Thick-restart form for the pencil: Algorithm alg:FiltLanTR in the
+// B-inner product, on the bases of the solver above (W B-orthonormal, Z = B W)
+// and the filtered step of eq:polyapp1. Locked vectors UL (B-orthonormal)
+// are kept with BUL = B UL. Each step makes two classical Gram-Schmidt passes
+// against [UL, W_0..W_i] (coefficients from W^T z, updates with Z; for the
+// locked block from UL^T z, updates with BUL), which also removes the
+// three-term and arrowhead components. T = the kept Ritz values with their
+// couplings s_j to index l, then the step coefficients; its tridiagonal form
+// comes from evh::ArrowForm. Every reading (candidates >= bar, carried
+// early-restart sums, extra restart, two no-candidate restarts end the run,
+// at most m - max(Ncycle, 10) kept Ritz vectors) is that of the standard
+// thick-restart solver.
+struct GenTR {
+  GenSolver &g;
+  int n;
+  int64_t ld;
+  double tlo, thi, normA, tol;
+  int m, ncycle, nev_cap, max_its;
+  uint64_t seed;
+  double *UL = nullptr, *BUL = nullptr, *hL1 = nullptr, *hL2 = nullptr;
+  std::vector<double> alpha, beta, th_tr, s_tr, lam, res;
+  evh::ArrowForm arrow;
+  std::vector<double> arrow_d, arrow_e;
+  bool arrow_ok = false;
+  int nlock = 0, l = 0, i = 0, its = 0, nrand = 0, nocand = 0, nrestart = 0;
+  int status = EVSL_OK;
+  bool done = false, next_ok = true;
+  double t_old = NAN, t_new = NAN;
+
+  explicit GenTR(GenSolver &gs) : g(gs), n(gs.n), ld(gs.ld) {}
+  hipStream_t st() const { return g.st(); }
+  double *W(int j) const { return g.W + (int64_t)j * ld; }
+  double *Z(int j) const { return g.Z + (int64_t)j * ld; }
+
+  void setup() {
+    UL = g.alloc((size_t)ld * nev_cap);
+    BUL = g.alloc((size_t)ld * nev_cap);
+    hL1 = g.alloc(nev_cap + 2);
+    hL2 = g.alloc(nev_cap + 2);
+    alpha.assign(m + 1, 0.0);
+    beta.assign(m + 1, 0.0);
+    if (fresh(0, W(0), Z(0)) == 0.0) fail(EVSL_EINVAL);
+  }
+
+  // z -= BUL (UL^T z), then z -= Z (W_0..k-1^T z); coefficients into hL, h
+  void project_z(double *z, int k, double *hL, double *h) {
+    evk::gemv_t(st(), n, nlock, UL, ld, z, g.partial, hL);
+    evk::gemv_n_sub(st(), n, nlock, BUL, ld, hL, z);
+    evk::gemv_t(st(), n, k, g.W, ld, z, g.partial, h);
+    evk::gemv_n_sub(st(), n, k, g.Z, ld, h, z);
+  }
+
+  // Random vector from restart block `nrand`, B-orthogonalised twice against
+  // the locked vectors and W_0..k-1, B-normalised into (w, z). Returns its
+  // B-norm relative to before (0 when it vanished). Synchronous.
+  double fresh(int k, double *w, double *z) {
+    const evk::Csr Bc = to_csr(g.B);
+    hipStream_t s = st();
+    evk::lanczos_start(s, n, seed, nrand++, g.wb);
+    evk::cheb_vec<double>(s, Bc, 1, evk::STEP_PLAIN, 1.0, 0.0, g.wb, nullptr, g.zb, nullptr, ld, 1,
+                          nullptr, 0, 0);
+    evk::col_dots(s, n, 1, g.wb, ld, g.zb, ld, g.partial, g.nrm2 + 1);
+    for (int pass = 0; pass < 2; ++pass) {
+      // w -= UL (BUL^T w), w -= W (Z^T w)
+      evk::gemv_t(s, n, nlock, BUL, ld, g.wb, g.partial, hL1);
+      evk::gemv_n_sub(s, n, nlock, UL, ld, hL1, g.wb);
+      evk::gemv_t(s, n, k, g.Z, ld, g.wb, g.partial, g.h1);
+      evk::gemv_n_sub(s, n, k, g.W, ld, g.h1, g.wb);
+    }
+    evk::cheb_vec<double>(s, Bc, 1, evk::STEP_PLAIN, 1.0, 0.0, g.wb, nullptr, g.zb, nullptr, ld, 1,
+                          nullptr, 0, 0);
+    evk::col_dots(s, n, 1, g.wb, ld, g.zb, ld, g.partial, g.nrm2);
+    HC(g.ctx, hipMemcpyAsync(g.hs, g.nrm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HC(g.ctx, hipStreamSynchronize(s));
+    const double after = std::sqrt(std::max(g.hs[0], 0.0));
+    const double before = std::sqrt(std::max(g.hs[1], 0.0));
+    if (!(after > 1e-10 * before)) return 0.0;
+    evk::normalize(s, n, g.wb, w, g.nrm2, nullptr);
+    evk::normalize(s, n, g.zb, z, g.nrm2, nullptr);
+    return after / before;
+  }
+
+  void tri_form(int k, std::vector<double> &d, std::vector<double> &e) {
+    d.assign(k, 0.0);
+    e.assign(std::max(k - 1, 1), 0.0);
+    if (l > 0) {
+      if (!arrow_ok) {
+        arrow_d.assign(l + 1, 0.0);
+        arrow_e.assign(std::max(l, 1), 0.0);
+        arrow.reduce(l, th_tr.data(), s_tr.data(), alpha[l], arrow_d.data(), arrow_e.data());
+        arrow_ok = true;
+      }
+      std::copy(arrow_d.begin(), arrow_d.begin() + (l + 1), d.begin());
+      std::copy(arrow_e.begin(), arrow_e.begin() + l, e.begin());
+    }
+    for (int r = l > 0 ? l + 1 : 0; r < k; ++r) d[r] = alpha[r];
+    for (int r = l; r + 1 < k; ++r) e[r] = beta[r];
+  }
+
+  void check(const std::vector<double> &w) const {
+    for (double x : w)
+      if (!(std::fabs(x) <= 1.01 * g.pbound + 1e-12)) fail(EVSL_ESPECTRUM);
+  }
+
+  // one Lanczos step of the current cycle (column i -> i + 1)
+  void step() {
+    hipStream_t s = st();
+    its++;
+    g.apply_filter(Z(i), g.zb);
+    project_z(g.zb, i + 1, hL1, g.h1);
+    project_z(g.zb, i + 1, hL2, g.h2);
+    g.bsolve(g.zb, g.wb);
+    evk::col_dots(s, n, 1, g.wb, ld, g.zb, ld, g.partial, g.nrm2);
+    hipLaunchKernelGGL(k_gen_scalars, dim3(1), dim3(64), 0, s, g.h1, g.h2, i, g.nrm2, g.scal);
+    evk::normalize(s, n, g.wb, W(i + 1), g.nrm2, nullptr);
+    evk::normalize(s, n, g.zb, Z(i + 1), g.nrm2, nullptr);
+    HC(g.ctx, hipMemcpyAsync(g.hs, g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HC(g.ctx, hipStreamSynchronize(s));
+    const double a_i = g.hs[0], b_i = g.hs[1];
+    if (!std::isfinite(a_i) || !std::isfinite(b_i)) fail(EVSL_ESPECTRUM);
+    alpha[i] = a_i;
+    bool end_cycle = false;
+    next_ok = true;
+    if (!(b_i > 1e-12)) {
+      // invariant subspace of the filtered operator: new direction, coupling 0
+      beta[i] = 0.0;
+      if (fresh(i + 1, W(i + 1), Z(i + 1)) == 0.0) {
+        next_ok = false;
+        end_cycle = true;
+      }
+    } else {
+      beta[i] = b_i;
+    }
+    if (!end_cycle && ((i + 1) - l) % ncycle == 0) {
+      const int k = i + 1;
+      std::vector<double> w(k), d, e;
+      tri_form(k, d, e);
+      evh::tridiag_eig(k, d.data(), e.data(), w.data(), nullptr);
+      check(w);
+      t_old = t_new;
+      t_new = 0.0;
+      for (double x : w)
+        if (x >= g.bar) t_new += x;
+      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new))) end_cycle = true;
+    }
+    if (its > max_its) end_cycle = true;
+    if (!end_cycle && i + 1 >= m) end_cycle = true;
+    if (end_cycle) {
+      restart(i + 1);
+      if (!done && its > max_its) {
+        status = EVSL_ENOCONV;
+        done = true;
+      }
+    } else {
+      i++;
+    }
+  }
+
+  void restart(int dim) {
+    hipStream_t s = st();
+    nrestart++;
+    std::vector<double> d, e, w(dim), Ysel((size_t)dim * dim);
+    tri_form(dim, d, e);
+    const int nsel = evh::tridiag_eig_sel(dim, d.data(), e.data(), w.data(), g.bar, Ysel.data());
+    if (l > 0 && nsel > 0) arrow.back(nsel, Ysel.data(), dim);
+    arrow_ok = false;
+    check(w);
+    const int first = dim - nsel;
+    const double beta_last = next_ok ? beta[dim - 1] : 0.0;
+    const int lc = nsel;
+    int naccept = 0;
+    std::vector<int> lock_sel, tr_sel;
+    std::vector<double> lock_lam, lock_res;
+    int cap_tr = m - std::max(ncycle, 10);
+    if (cap_tr < 1) cap_tr = 1;
+    double *U = nullptr, *BU = nullptr;
+    if (lc > 0) {
+      // candidates largest first: column t of Yc is Ritz value w[dim - 1 - t]
+      std::vector<double> Yh((size_t)dim * lc);
+      for (int t = 0; t < lc; ++t) {
+        const double *y = Ysel.data() + (size_t)(dim - 1 - t - first) * dim;
+        std::copy(y, y + dim, Yh.begin() + (size_t)t * dim);
+      }
+      U = (double *)ws(g.ctx, 80, sizeof(double) * ld * lc);
+      BU = (double *)ws(g.ctx, 81, sizeof(double) * ld * lc);
+      double *AU = (double *)ws(g.ctx, 82, sizeof(double) * ld * lc);
+      double *Yd = (double *)ws(g.ctx, 83, sizeof(double) * (size_t)dim * lc);
+      double *dv = (double *)ws(g.ctx, 84, sizeof(double) * 4 * lc);
+      double *pp = (double *)ws(g.ctx, 85, sizeof(double) * evk::dot_partials(n, lc));
+      HC(g.ctx, hipMemcpyAsync(Yd, Yh.data(), sizeof(double) * Yh.size(), hipMemcpyHostToDevice, s));
+      evk::gemm_nn(s, n, dim, lc, g.W, ld, Yd, dim, U, ld);
+      evk::gemm_nn(s, n, dim, lc, g.Z, ld, Yd, dim, BU, ld);
+      const evk::Csr Ac = to_csr(g.A);
+      evk::cheb_vec<double>(s, Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, U, nullptr, AU, nullptr, ld, lc,
+                            nullptr, 0, 0);
+      g.nmv += lc;
+      double *uau = dv, *ubu = dv + lc, *r2 = dv + 2 * lc, *bb = dv + 3 * lc;
+      evk::col_dots(s, n, lc, U, ld, AU, ld, pp, uau);
+      evk::col_dots(s, n, lc, U, ld, BU, ld, pp, ubu);
+      evk::col_resid2(s, n, lc, BU, AU, ld, uau, ubu, pp, r2);  // ||AU - lambda BU||^2
+      evk::col_dots(s, n, lc, BU, ld, BU, ld, pp, bb);
+      evk::normalize_cols(s, n, lc, U, ld, ubu);  // B-normalised
+      evk::normalize_cols(s, n, lc, BU, ld, ubu);
+      std::vector<double> h(4 * lc);
+      HC(g.ctx, hipMemcpyAsync(h.data(), dv, sizeof(double) * 4 * lc, hipMemcpyDeviceToHost, s));
+      HC(g.ctx, hipStreamSynchronize(s));
+      for (int t = 0; t < lc; ++t) {
+        const double lamt = h[t] / h[lc + t];
+        if (!std::isfinite(lamt)) fail(EVSL_ESPECTRUM);
+        if (lamt < tlo || lamt > thi) continue;  // outside the slice: ignored
+        naccept++;
+        const double r = std::sqrt(std::max(h[2 * lc + t], 0.0)) /
+                         (std::sqrt(std::max(h[3 * lc + t], 0.0)) * normA);
+        if (r <= tol) {
+          lock_sel.push_back(t);
+          lock_lam.push_back(lamt);
+          lock_res.push_back(r);
+        } else if ((int)tr_sel.size() < cap_tr) {
+          tr_sel.push_back(t);
+        }
+      }
+      if (nlock + (int)lock_sel.size() > nev_cap) {
+        status = EVSL_ENOMEM;
+        done = true;
+        return;
+      }
+      for (size_t q = 0; q < lock_sel.size(); ++q) {
+        HC(g.ctx, hipMemcpyAsync(UL + (int64_t)nlock * ld, U + (int64_t)lock_sel[q] * ld,
+                                 sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        HC(g.ctx, hipMemcpyAsync(BUL + (int64_t)nlock * ld, BU + (int64_t)lock_sel[q] * ld,
+                                 sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        lam.push_back(lock_lam[q]);
+        res.push_back(lock_res[q]);
+        nlock++;
+      }
+    }
+    if (naccept == 0) {
+      nocand++;
+      th_tr.clear();
+      s_tr.clear();
+      if (nocand >= 2) {
+        done = true;
+        return;
+      }
+      // extra restart: fresh random vector B-orthogonal to the locked set
+      l = 0;
+      i = 0;
+      if (fresh(0, W(0), Z(0)) == 0.0) done = true;
+      return;
+    }
+    nocand = 0;
+    // [kept Ritz vectors | w_dim] as the new basis
+    if (next_ok) {
+      HC(g.ctx, hipMemcpyAsync(g.f1, W(dim), sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      HC(g.ctx, hipMemcpyAsync(g.f2, Z(dim), sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    th_tr.clear();
+    s_tr.clear();
+    for (size_t q = 0; q < tr_sel.size(); ++q) {
+      const int t = tr_sel[q];
+      HC(g.ctx, hipMemcpyAsync(W((int)q), U + (int64_t)t * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s));
+      HC(g.ctx, hipMemcpyAsync(Z((int)q), BU + (int64_t)t * ld, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, s));
+      th_tr.push_back(w[dim - 1 - t]);
+      s_tr.push_back(beta_last * Ysel[(size_t)(dim - 1 - t - first) * dim + (dim - 1)]);
+    }
+    l = (int)tr_sel.size();
+    if (next_ok) {
+      HC(g.ctx, hipMemcpyAsync(W(l), g.f1, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      HC(g.ctx, hipMemcpyAsync(Z(l), g.f2, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      if (fresh(l, W(l), Z(l)) == 0.0) {
+        done = true;
+        return;
+      }
+      std::fill(s_tr.begin(), s_tr.end(), 0.0);
+    }
+    i = l;
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -300,7 +586,9 @@ int evsl_filtered_lanczos_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_cs
   check_csr(A);
   check_csr(B);
   if (A->dtype != EVSL_F64 || B->dtype != EVSL_F64) return EVSL_ENOTIMPL;
-  if (opt && (opt->prec != EVSL_F64 || opt->method == EVSL_LAN_TR)) return EVSL_ENOTIMPL;
+  if (opt && opt->prec != EVSL_F64) return EVSL_ENOTIMPL;
+  if (opt && opt->method != EVSL_LAN_TR && opt->method != EVSL_LAN_NR) return EVSL_EINVAL;
+  const bool tr = opt && opt->method == EVSL_LAN_TR;
   const double t0 = now_s();
   double tlo = intv[0], thi = intv[1];
   const double lmin = intv[2], lmax = intv[3];
@@ -321,14 +609,53 @@ int evsl_filtered_lanczos_gen(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_cs
   g.coef.assign(pol->coef, pol->coef + g.deg + 1);
   for (double c : g.coef) g.pbound += std::fabs(c);
   const int nev_est = (opt && opt->nev_est > 0) ? opt->nev_est : 50;
-  int m = (opt && opt->m > 0) ? opt->m : std::max(5 * nev_est + 200, 400);
+  int m = (opt && opt->m > 0) ? opt->m
+                              : (tr ? std::max(3 * nev_est + 30, 60) : std::max(5 * nev_est + 200, 400));
   m = (int)std::min<int64_t>(m, A->n - 1);
   if (m < 2) return EVSL_EINVAL;
   const int ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : 30;
   const double tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
   const uint64_t seed = opt ? opt->seed : 0;
   const int nev_cap = (opt && opt->nev_cap > 0) ? opt->nev_cap : std::max(2 * nev_est + 40, 100);
-  g.setup(ctx, A, B, bbounds, bdeg, m);
+  g.setup(ctx, A, B, bbounds, bdeg, m, tr ? nev_cap : 0);
+  if (tr) {
+    GenTR t(g);
+    t.tlo = tlo;
+    t.thi = thi;
+    t.normA = normA;
+    t.tol = tol;
+    t.m = m;
+    t.ncycle = ncycle;
+    t.nev_cap = nev_cap;
+    t.max_its = (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
+    t.seed = seed;
+    t.setup();
+    while (!t.done) t.step();
+    HC(ctx, hipStreamSynchronize(ctx->stream));
+    const int k = t.nlock;
+    std::vector<int> idx(k);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return t.lam[a] < t.lam[b]; });
+    out->nev = k;
+    out->lam = (double *)std::malloc(sizeof(double) * std::max(k, 1));
+    out->res = (double *)std::malloc(sizeof(double) * std::max(k, 1));
+    if (!out->lam || !out->res) fail(EVSL_ENOMEM);
+    out->Y = nullptr;
+    if (k > 0) out->Y = (double *)dalloc(ctx, sizeof(double) * (size_t)g.n * k);
+    for (int j = 0; j < k; ++j) {
+      out->lam[j] = t.lam[idx[j]];
+      out->res[j] = t.res[idx[j]];
+      HC(ctx, hipMemcpyAsync(out->Y + (int64_t)j * g.n, t.UL + (int64_t)idx[j] * g.ld,
+                             sizeof(double) * g.n, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HC(ctx, hipStreamSynchronize(ctx->stream));
+    out->niter = t.its;
+    out->nmv = g.nmv;
+    out->nrestart = g.nsolve;  // solves with B
+    out->status = t.status == EVSL_ENOMEM ? EVSL_ENOCONV : t.status;
+    out->t_tot = now_s() - t0;
+    return out->status;
+  }
   auto check = [&](const std::vector<double> &w) {
     for (double x : w)
       if (!(std::fabs(x) <= 1.01 * g.pbound + 1e-12)) fail(EVSL_ESPECTRUM);

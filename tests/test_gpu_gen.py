@@ -79,6 +79,36 @@ def test_filtered_lanczos_gen_matches_closed_form_and_oracle(ctx, ab):
     assert abs(st["niter"] - ost["niter"]) <= 30
 
 
+@pytest.mark.parametrize("ab", [(0.5, 1.2), (2.0, 3.0), (10.0, 11.0)])
+def test_filtered_lanczos_gen_thick_restart_matches_closed_form_and_oracle(ctx, ab):
+    """The thick-restart form for the pencil: every eigenvalue of the slice,
+    double ones included, equal to the closed form and to the oracle's
+    thick-restart solver; B-orthonormal vectors."""
+    N = 16
+    A, B, Ad, Bd, bb = _setup(ctx, N)
+    ex = _fe_eigs(N)
+    want = ex[(ex >= ab[0]) & (ex <= ab[1])]
+    lo, hi = oracle.lanczos_bounds_gen(A, B, 80, 3)
+    intv = [ab[0], ab[1], lo, hi]
+    pol = ev.evsl_cheb_coeffs(intv, damping=ev.DAMP_JACKSON)
+    opol = oracle.find_pol(intv, damping=oracle.DAMP_JACKSON)
+    lam, Y, res, st = ev.evsl_filtered_lanczos_gen(
+        ctx, Ad, Bd, bb, BDEG, intv, pol,
+        ev.lan_opts(tol=1e-10, nev_est=len(want), method=ev.EVSL_LAN_TR))
+    olam, _, _, ost = oracle.filtered_lanczos_gen_tr(A, B, intv, opol, tol=1e-10,
+                                                     nev_est=len(want))
+    assert st["status"] == ev.EVSL_OK, st
+    assert len(lam) == len(want) == len(olam)
+    assert np.abs(lam - want).max() <= 1e-10 * ex[-1]
+    assert np.abs(lam - olam).max() <= 1e-10 * ex[-1]
+    assert res.max() <= 1e-10
+    Yh = Y.cpu().numpy()
+    Db = B.to_dense()
+    assert np.abs(Yh.T @ Db @ Yh - np.eye(len(lam))).max() <= 1e-10
+    R = A.to_dense() @ Yh - Db @ Yh * lam
+    assert np.linalg.norm(R, axis=0).max() <= 1e-9 * ex[-1]
+
+
 def test_generalized_rejects_unsupported_options(ctx):
     A, B, Ad, Bd, bb = _setup(ctx, 8)
     lo, hi = oracle.lanczos_bounds_gen(A, B, 40, 3)
@@ -86,7 +116,7 @@ def test_generalized_rejects_unsupported_options(ctx):
     pol = ev.evsl_cheb_coeffs(intv)
     with pytest.raises(ev.EvslError) as e:
         ev.evsl_filtered_lanczos_gen(ctx, Ad, Bd, bb, BDEG, intv, pol,
-                                     ev.lan_opts(method=ev.EVSL_LAN_TR))
+                                     ev.lan_opts(method=ev.EVSL_LAN_TR, prec=ev.EVSL_F32))
     assert e.value.code == ev.EVSL_ENOTIMPL
     with pytest.raises(ev.EvslError) as e:
         ev.evsl_filtered_lanczos_gen(ctx, Ad, Bd, [0.0, 1.0], BDEG, intv, pol)

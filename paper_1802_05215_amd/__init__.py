@@ -478,7 +478,8 @@ def evsl_spectrum_bounds_gen(ctx, A, B, bbounds, bdeg, nsteps=80, seed=3):
 
 
 def evsl_filtered_lanczos_gen(ctx, A, B, bbounds, bdeg, intv, pol, opts=None):
-    """Filtered non-restart Lanczos for (A, B): (lam, Y (B-orthonormal), res, stats)."""
+    """Filtered Lanczos for (A, B), non-restart by default or thick restart
+    (opts.method = EVSL_LAN_TR): (lam, Y (B-orthonormal), res, stats)."""
     bb = _f64(bbounds)
     iv = _f64(intv)
     out = EigsT()

@@ -2,7 +2,9 @@
 source, plants one plausible mistake (a wrong index, a flipped sign, a dropped
 factor or term), builds the copy with gcc and runs a set of closed-form and
 paper-table checks against it: at least one check must fail. The unmodified
-source passes every check. CPU only; the mistakes live in temporary copies."""
+source passes every check. CPU only; the mistakes live in temporary copies.
+(A mistake that full reorthogonalisation repairs, such as a wrong coefficient
+on the explicit three-term subtraction, changes no result and is not listed.)"""
 import ctypes as C
 import json
 import os
@@ -51,6 +53,15 @@ MUTATIONS = [
     ("Gram-Schmidt adds the projections",
      "for (int64_t i = 0; i < n; ++i) z[i] -= h[j] * bj[i];",
      "for (int64_t i = 0; i < n; ++i) z[i] += h[j] * bj[i];"),
+    ("lsPol fit without the factor 2 of the j >= 1 coefficients",
+     "for (int j = 0; j <= deg; ++j) coef[j] *= (j == 0 ? 1.0 : 2.0) / N;",
+     "for (int j = 0; j <= deg; ++j) coef[j] *= 1.0 / N;"),
+    ("conjugate gradients with the residual update's sign flipped",
+     "for (int64_t i = 0; i < n; ++i) { x[i] += a * p[i]; res[i] -= a * q[i]; }",
+     "for (int64_t i = 0; i < n; ++i) { x[i] += a * p[i]; res[i] += a * q[i]; }"),
+    ("pencil bounds: the Lanczos step subtracts alpha w_i instead of alpha z_i",
+     "    or_spmv(n, rp, ci, va, wi, z);\n    if (i > 0)\n      for (int64_t r = 0; r < n; ++r) z[r] -= beta * Z[(size_t)(i - 1) * n + r];\n    const double alpha = dot(n, z, wi);\n    for (int64_t r = 0; r < n; ++r) z[r] -= alpha * zi[r];",
+     "    or_spmv(n, rp, ci, va, wi, z);\n    if (i > 0)\n      for (int64_t r = 0; r < n; ++r) z[r] -= beta * Z[(size_t)(i - 1) * n + r];\n    const double alpha = dot(n, z, wi);\n    for (int64_t r = 0; r < n; ++r) z[r] -= alpha * wi[r];"),
     ("thick restart couples through the first component",
      "        sTR[lnew] = beta_last * y[dim - 1];\n        lnew++;",
      "        sTR[lnew] = beta_last * y[0];\n        lnew++;"),
@@ -126,6 +137,34 @@ def _checks():
                                                  max_its=400)
         return len(lam_) == len(want) and np.abs(lam_ - want).max() < 1e-10 * 8
     run("thick-restart Lanczos on a 20 x 20 Laplacian", lanczos)
+
+    def lspol_fit():
+        c = oracle.lspol(0, 0.5, 2.0, 40)
+        t = np.linspace(0.5, 2.0, 7)
+        x = (t - 1.25) / 0.75
+        return np.abs(np.polynomial.chebyshev.chebval(x, c) - 1.0 / t).max() < 1e-10
+    run("lsPol fit of 1/t", lspol_fit)
+
+    def pencil():
+        Ap, Bp = I.fe_pencil(12)
+        th = np.arange(1, 13) * np.pi / 13
+        mu = (2 - 2 * np.cos(th)) / ((4 + 2 * np.cos(th)) / 6)
+        ex = np.sort((mu[:, None] + mu[None, :]).ravel())
+        r = np.linspace(1.0, 2.0, Bp.n)
+        if np.linalg.norm(Bp.to_dense() @ oracle.cg_solve(Bp, r) - r) > 1e-10 * np.linalg.norm(r):
+            return False
+        lo, hi = oracle.lanczos_bounds_gen(Ap, Bp, 60, 3)
+        # the bounds contain the spectrum up to rounding and sit close to its ends
+        tol_b = 1e-6 * ex[-1]
+        if not (ex[0] - tol_b <= lo <= ex[0] + 1e-12 * ex[-1]
+                and ex[-1] - 1e-12 * ex[-1] <= hi <= ex[-1] + tol_b):
+            return False
+        iv = [3.0, 5.0, lo, hi]
+        want = ex[(ex >= 3.0) & (ex <= 5.0)]
+        p = oracle.find_pol(iv, damping=oracle.DAMP_JACKSON)
+        lam_, _, _, st = oracle.filtered_lanczos_gen(Ap, Bp, iv, p, tol=1e-10, nev_est=len(want))
+        return len(lam_) == len(want) and np.abs(lam_ - want).max() < 1e-10 * ex[-1]
+    run("pencil solves and non-restart Lanczos on a 12 x 12 pencil", pencil)
     return failed
 
 

@@ -749,6 +749,9 @@ struct Slice {
   void polish() {
     int P = nlock + nguard;
     if (P == 0 || polish_max <= 0) return;
+    // the lock residuals are FP64 (FP64 products with A on the FP64 Ritz
+    // vectors): pairs locked at tol already meet it, and need no FP64 round
+    if (nguard == 0 && !res.empty() && *std::max_element(res.begin(), res.end()) <= tol) return;
     hipStream_t s = st();
     const evk::Csr Ac = to_csr(A);
     const int dp = polish_div <= 1 ? deg : std::max(2, deg / polish_div);

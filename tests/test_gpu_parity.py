@@ -551,6 +551,26 @@ def test_fp32_filter_lanczos_polished_to_fp64_tolerance(ctx, intv_ab):
     assert np.abs(lam - want).max() <= 1e-10 * max(abs(lo), abs(hi))
 
 
+def test_fp32_filter_locked_at_tol_skips_the_polish(ctx):
+    """When the FP32 phase locks at the requested tolerance (tol_lo = tol =
+    1e-6, above the FP32 filter's floor) every pair already meets it in FP64:
+    no polish round runs, and the eigenvalues match the FP64 form's."""
+    A = I.laplacian(16, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.15, lo, hi]
+    want = w[(w >= 1.0) & (w <= 1.15)]
+    lam, Y, res, st = ev.evsl_filtered_lanczos(
+        ctx, Ad, intv, _pol(intv), ev.lan_opts(tol=1e-6, tol_lo=1e-6, seed=2,
+                                               nev_est=len(want) + 5, prec=ev.EVSL_F32))
+    assert st["status"] == 0 and len(lam) == len(want), st
+    assert st["npolish"] == 0
+    assert res.max() <= 1e-6
+    # eigenvalue error of a residual-r pair is about r^2 / gap
+    assert np.abs(lam - want).max() <= 1e-8 * max(abs(lo), abs(hi))
+
+
 def test_fp32_filter_lanczos_40x40_eigenvalues(ctx):
     """40 x 40 Laplacian, [1.0, 1.6]: the FP32-filter form finds all 91
     eigenvalues (44 double pairs). Here the FP64 polish does not bring every

@@ -12,7 +12,14 @@ seed 0); all eigenvalues in [0.60, 0.70], cut into 10 slices by a KPM density
 estimate (degree 80, 20 Rademacher vectors, Jackson damping); Jackson
 filters with tau = 0.8; tolerance 1e-8 on ||A u - lambda u|| / ||A||.
 
-Prints one JSON line (see the keys below).
+The default run does one warm-up solve, then whole timed solves while the
+next one still ends before --time-budget seconds from the start (at most
+--steps), then the batched 200^3 filter leg (one FP64 Clenshaw degree step
+over a 512-column block per launch, reported under "c3_filter"), then the
+oracle's bounded sample ("cpu_baseline"). Only slices whose solver status is
+EVSL_OK count towards eigenpairs/s.
+
+Prints one JSON line (see the keys below); progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -27,6 +34,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+T_START = time.perf_counter()
 METRIC = "eigenpairs/s + filter SpMM HBM GB/s at resid<=1e-8; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 
@@ -34,8 +42,21 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="at most this many timed solves (fewer when --time-budget ends them)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up solves (at most 1 is run)")
+    ap.add_argument("--time-budget", type=float, default=330.0,
+                    help="seconds from the start after which no further timed solve begins "
+                         "(0: run all --steps)")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip the 200^3 x 512-column filter leg of the default run")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="only the 200^3 x 512-column filter leg (its own JSON line)")
+    ap.add_argument("--c3-degree", type=int, default=24,
+                    help="200^3 leg: degree of the truncated filters (launches per application "
+                         "= degree + 1)")
+    ap.add_argument("--c3-launches", type=int, default=25,
+                    help="200^3 leg: at least this many timed launches")
     ap.add_argument("--grid", type=int, default=100, help="N of the N^3 grid")
     ap.add_argument("--interval", type=float, nargs=2, default=[0.60, 0.70])
     ap.add_argument("--nslices", type=int, default=10)
@@ -61,9 +82,10 @@ def parse():
     ap.add_argument("--group-width", type=int, default=-1,
                     help="slices per block filter launch (-1: autotuned, 0: all)")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64",
-                    help="filter arithmetic (f32: precision form with FP64 polish)")
+                    help="filter arithmetic (f32: precision form, FP32 phase then FP64 phase)")
     ap.add_argument("--tol-lo", type=float, default=0.0, help="FP32-phase lock tolerance")
-    ap.add_argument("--polish-div", type=int, default=0, help="polish filter degree divisor")
+    ap.add_argument("--precision-out", default="",
+                    help="--precision-study: write the per-eigenvalue table (CSV) here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain copy kernel (1 GiB) used to calibrate counters")
     ap.add_argument("--method", choices=["tr", "nr", "si"], default="tr",
@@ -104,6 +126,10 @@ def parse():
     ap.add_argument("--calib", type=int, default=4, help="requests served alone to calibrate")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-running", type=int, default=4)
+    ap.add_argument("--max-bypass", type=int, default=8,
+                    help="serving: times a waiting head request may be passed over")
+    ap.add_argument("--serve-prec", choices=["f32", "f64"], default="f32",
+                    help="serving: FP32-filter precision form (default) or FP64")
     ap.add_argument("--serve-log", default="",
                     help="serving: append one JSON record per finished request to this file")
     return ap.parse_args()
@@ -162,7 +188,7 @@ def one_step(ctx, ev, Ad, args):
                                     m=int(args.m_factor * nev_est) + 30 if args.m_factor else 0,
                                     max_its=args.max_its,
                                     prec=ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64,
-                                    tol_lo=args.tol_lo, polish_div=args.polish_div,
+                                    tol_lo=args.tol_lo,
                                     method=ev.EVSL_LAN_NR if args.method == "nr" else ev.EVSL_LAN_TR))
     if args.group_width < 0:
         gw, us = ev.evsl_autotune(ctx, Ad, len(sel),
@@ -190,9 +216,13 @@ def one_step(ctx, ev, Ad, args):
         # a slice that starts at the lower spectrum bound owns everything below it
         keep = ((lam >= ivs[q][0]) | (ivs[q][0] <= ivs[q][2])) & ((lam < ivs[q][1]) | last) \
             & (res <= args.tol)
+        if st["status"] != ev.EVSL_OK:
+            # an unconverged slice may miss eigenpairs: none of its pairs count
+            keep &= False
         lams.append(lam[keep])
         ress.append(res[keep])
         per_slice.append(dict(slice=sel[q], deg=pols[q].deg, nev=int(keep.sum()), niter=st["niter"],
+                              nev_est=opts[q].nev_est,
                               nmv=st["nmv"], t_done=st["t_tot"], t_mv=st["t_mv"],
                               t_orth=st["t_orth"], t_ritz=st["t_ritz"], status=st["status"],
                               npolish=st["npolish"]))
@@ -202,32 +232,159 @@ def one_step(ctx, ev, Ad, args):
                 per_slice=per_slice, pols=pols, ivs=ivs)
 
 
-def cpu_baseline(A, rec, args):
-    """The oracle, timed on the host's cores, on a bounded sample: one full
-    filter application of the highest-degree slice on the full matrix. The
-    oracle's eigenpairs/s is then extrapolated from the Lanczos step counts of
-    the GPU run (filter work only)."""
+def host_info():
+    """CPU model and logical core count of this host (for the oracle timings)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
+def cpu_baseline(A, rec, args, c3=None, budget_s=25.0):
+    """The oracle, timed on this host's cores, on a bounded sample of the
+    default workload: its thick-restart filtered Lanczos (Algorithm
+    alg:FiltLanTR) on the highest-degree slice of the GPU run's cut, stopped
+    after a fixed number of Lanczos steps (filter, deflation, full
+    reorthogonalisation, as in a full solve). Its time per Lanczos step per
+    filter degree is then scaled to the Lanczos steps and degrees of every
+    slice of the GPU run. The early steps reorthogonalise against a short
+    basis, so the scaled time is a lower bound on the oracle's full solve
+    and the rate an upper bound. With the 200^3 filter leg, the oracle also
+    filters one column of that block (one of its degree-k filters), checked
+    against the GPU's column."""
     import oracle
+    model, nproc = host_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or nproc
+    oracle.lib()
     q = int(np.argmax([p.deg for p in rec["pols"]]))
     p = rec["pols"][q]
-    v = np.random.default_rng(0).standard_normal(A.n)
-    oracle.lib()
+    iv = rec["ivs"][q]
+    opol = oracle.find_pol(iv, damping=2, tau=0.8, tau_ext=0.4)
+    ps = rec["per_slice"][q]
+    # one filter application (deg products with A) to size the sample
     t0 = time.perf_counter()
-    oracle.filter_apply(A, p.cc, p.dd, p.coef, v)
+    oracle.filter_apply(A, p.cc, p.dd, p.coef, np.ones(A.n))
+    t_filter = time.perf_counter() - t0
+    steps = int(max(2, min(40, budget_s / max(t_filter, 1e-3))))
+    t0 = time.perf_counter()
+    _, _, _, ost = oracle.filtered_lanczos(A, iv, opol, tol=args.tol, seed=2 + ps["slice"],
+                                           max_its=steps, nev_est=ps["nev_est"])
     dt = time.perf_counter() - t0
-    per_step = dt / p.deg
-    # products with A of the GPU run (filter degree-steps, one per column, plus
-    # the Rayleigh-Ritz products)
-    steps = sum(s["nmv"] for s in rec["per_slice"])
-    est_time = per_step * steps
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": rec["nev"] / est_time, "unit": "eigenpairs/s", "cores": cores,
-            "kind": "oracle",
-            "sample": (f"one oracle filter application, degree {p.deg}, on the full matrix "
-                       f"({dt:.2f} s, {per_step * 1e3:.2f} ms per degree step); extrapolated to "
-                       f"the {steps} products with A of the GPU run; filter work only "
-                       f"(reorthogonalisation and Rayleigh-Ritz excluded), so an upper bound on "
-                       f"the oracle's rate")}
+    per_step_deg = dt / max(ost["niter"], 1) / opol["deg"]
+    est_time = sum(s["niter"] * s["deg"] for s in rec["per_slice"]) * per_step_deg
+    out = {"value": rec["nev"] / est_time, "unit": "eigenpairs/s", "cores": threads,
+           "kind": "oracle", "host_cpu": model, "host_nproc": nproc,
+           "sample": (f"oracle thick-restart filtered Lanczos on slice {ps['slice']} "
+                      f"(degree {opol['deg']}) of the same cut, on the full 100^3 matrix, stopped "
+                      f"after {ost['niter']} Lanczos steps ({dt:.1f} s, "
+                      f"{per_step_deg * 1e3:.3f} ms per step per degree); scaled to the "
+                      f"{sum(s['niter'] for s in rec['per_slice'])} Lanczos steps x degree of "
+                      f"all slices of the GPU run ({est_time:.0f} s). Early steps reorthogonalise "
+                      f"against a short basis, so this rate is an upper bound on the oracle's")}
+    if c3 is not None and c3.get("check_column") is not None:
+        col = c3.pop("check_column")
+        t0 = time.perf_counter()
+        yo = oracle.filter_apply(c3.pop("A_host"), col["cc"], col["dd"], col["coef"], col["v"])
+        out["c3_column_check"] = {
+            "rel_err_vs_oracle": float(np.linalg.norm(col["y"] - yo) / np.linalg.norm(col["v"])),
+            "degree": len(col["coef"]) - 1, "column": col["index"],
+            "oracle_s": time.perf_counter() - t0}
+    return out
+
+
+def c3_filter_leg(ctx, ev, args, log):
+    """The batched 200^3 workload's filter step: 3-D 7-point Laplacian 200^3 +
+    U[0,1) potential (seed 0), interval [lambda_min, eta] with eta where the
+    KPM count (degree 80, 20 probes) reaches 512, cut into 32 KPM slices; the
+    512-column block (16 columns per slice, Gaussian, torch generator seed 0)
+    filtered by one Clenshaw degree step per launch over all 512 columns
+    (FP64). Every slice's filter is truncated to the same degree so that each
+    timed launch is a full-width step; the slices' own degrees are reported
+    beside. Times come from HIP events on the context stream around the filter
+    application (k + 1 launches, the two zero fills of the Clenshaw buffers
+    included in time and bytes)."""
+    import concurrent.futures as cf
+    import torch
+
+    import evsl_inputs as I
+    t0 = time.perf_counter()
+    N, ncols, nsl, kstep = 200, 512, 32, args.c3_degree
+    A = I.laplacian(N, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A, device="cuda:0")
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    mom, _ = ev.evsl_kpm_dos(ctx, Ad, [lo, hi, lo, hi], 80, 20, seed=1,
+                             damping=ev.DAMP_JACKSON)
+    cnt = lambda x0, x1: ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, x0, x1)
+    a, b = lo, hi
+    for _ in range(60):
+        mid = 0.5 * (a + b)
+        a, b = (mid, b) if cnt(lo, mid) < 512 else (a, mid)
+    eta = 0.5 * (a + b)
+    sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, [lo, eta, lo, hi], nsl, 2000)
+    ivs = [[sli[q], sli[q + 1], lo, hi] for q in range(nsl)]
+    with cf.ThreadPoolExecutor(8) as ex:
+        real = list(ex.map(lambda iv: ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON), ivs))
+    pols = [ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON, max_deg=kstep) for iv in ivs]
+    assert all(p.deg == kstep for p in pols)
+    cg = np.arange(ncols) // (ncols // nsl)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0)
+    V = torch.randn((A.n, ncols), dtype=torch.float64, device="cuda:0", generator=g)
+    Y = torch.empty_like(V)
+    # the block filter's launch schedule for this matrix and width (kept in ctx)
+    sched = ev.evsl_autotune_schedule(ctx, Ad, ncols, ev.EVSL_F64)
+    t_setup = time.perf_counter() - t0
+    ev.evsl_filter_apply(ctx, Ad, pols, cg, V, Y)  # warm-up
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    reps = max(1, -(-args.c3_launches // (kstep + 1)))
+    for _ in range(reps):
+        ev.evsl_filter_apply(ctx, Ad, pols, cg, V, Y)
+    torch.cuda.synchronize()
+    fs = ctx.filter_stats()
+    ctx.reset_stats()
+    gbps = fs["bytes"] / fs["seconds"] / 1e9
+    m_a = 12.0 * A.nnz + 4.0 * (A.n + 1)
+    step_bytes = m_a + 4.0 * A.n * ncols * 8
+    out = {
+        "workload": (f"batched filter: 3-D 7-point Laplacian {N}^3 + U[0,1) potential (seed 0), "
+                     f"[lambda_min, eta_512] = [{lo:.6g}, {eta:.6g}] cut into {nsl} KPM slices, "
+                     f"{ncols} columns ({ncols // nsl} per slice), FP64 Clenshaw degree step "
+                     f"over all {ncols} columns per launch"),
+        "n": A.n, "nnz": A.nnz, "columns": ncols,
+        "slice_degrees": [p.deg for p in real],
+        "timed_degree": kstep, "launches": fs["launches"],
+        "schedule": {"map": sched[0], "chunk_cols": sched[1], "group": sched[2],
+                     "tuner_ms_per_step": sched[3]},
+        "ms_per_launch": fs["seconds"] / fs["launches"] * 1e3,
+        "bytes_per_step": step_bytes,
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cheb_blk_lds<double, STEP_CLEN> at 512 columns"},
+        "setup_s": t_setup,
+    }
+    log(f"[c3] {fs['launches']} launches, {out['ms_per_launch']:.2f} ms each, {gbps:.0f} GB/s "
+        f"({gbps / HBM_PEAK_GBS:.2f} of peak); degrees {min(out['slice_degrees'])}-"
+        f"{max(out['slice_degrees'])}")
+    if not args.no_cpu_baseline:
+        j = int(ncols // 2)
+        p = pols[cg[j]]
+        out["check_column"] = {"index": j, "v": V[:, j].cpu().numpy(), "y": Y[:, j].cpu().numpy(),
+                               "cc": p.cc, "dd": p.dd, "coef": p.coef}
+        out["A_host"] = A
+    del V, Y
+    ctx.set_block_schedule(1, 0, 1)
+    torch.cuda.empty_cache()
+    return out
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1802_05215_amd", "csrc", "kernels.hip")
@@ -619,47 +776,119 @@ def pencil_main(args):
         "rows": rows}), flush=True)
 
 
+def match_eigs(ref, got):
+    """Pairs every reference eigenvalue with the nearest unused computed one
+    (both sorted; equal counts pair in order). Returns (pairs (i_ref, i_got),
+    reference indices left unmatched, computed indices left unmatched)."""
+    ref, got = np.asarray(ref), np.asarray(got)
+    if len(ref) == len(got):
+        return [(k, k) for k in range(len(ref))], [], []
+    used = np.zeros(len(got), bool)
+    pairs, miss = [], []
+    for k, x in enumerate(ref):
+        cand = np.where(~used)[0]
+        if len(cand) == 0:
+            miss.append(k)
+            continue
+        j = cand[np.argmin(np.abs(got[cand] - x))]
+        if abs(got[j] - x) <= 1e-6 * max(abs(x), 1.0):
+            used[j] = True
+            pairs.append((k, int(j)))
+        else:
+            miss.append(k)
+    return pairs, miss, [int(j) for j in np.where(~used)[0]]
+
+
 def precision_main(args, ctx, ev, Ad, A):
-    """The precision form against FP64 on single slices whose Jackson degrees
-    span about 50-300: for each slice, both solves from the same bounds, KPM and
-    filter; eigenvalues matched in order, the FP32 form's error reported
-    against FP64 for every eigenvalue (max and median, relative to ||A||)."""
+    """The precision form (FP32 filter phase, then the FP64 phase) against the
+    plain FP64 path on the same bounds, KPM, slices and filters: the 100^3
+    workload's ten slices of [0.60, 0.70] (one batch each) and three single
+    slices whose Jackson degrees span about 40-300 ([0.50, 0.60], [0.60, 0.65],
+    [0.60, 0.625]). For every eigenvalue: |lambda_32 - lambda_64| / |lambda_64|
+    (matched in order, or to the nearest when the counts differ, the unmatched
+    ones listed), and for the slices the oracle solved (tests/golden, slices 0
+    and 9 of the 100^3 cut) the same against the oracle's eigenvalues. Writes
+    the per-eigenvalue table to --precision-out when given."""
     import copy
     import torch
 
-    ivs = [(0.50, 0.60), (0.60, 0.65), (0.60, 0.625)]
-    out = []
-    for iv in ivs:
-        rec = {"interval": list(iv)}
-        lams = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else {"solved": {}}
+    runs = [("100^3 [0.60, 0.70], 10 KPM slices", [0.60, 0.70], 10)]
+    runs += [(f"single slice [{a:.3f}, {b:.3f}]", [a, b], 1)
+             for a, b in ((0.50, 0.60), (0.60, 0.65), (0.60, 0.625))]
+    out, table = [], []
+    for name, iv, ns in runs:
+        rec = {"workload": name, "interval": iv}
+        res_ = {}
         for prec in ("f64", "f32"):
             a = copy.copy(args)
-            a.interval, a.nslices, a.prec, a.slices, a.interval_count = list(iv), 1, prec, None, 0
+            a.interval, a.nslices, a.prec, a.slices, a.interval_count = list(iv), ns, prec, None, 0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = one_step(ctx, ev, Ad, a)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            lams[prec] = r["lam"]
-            ps = r["per_slice"][0]
-            rec[prec] = {"nev": r["nev"], "s": dt, "deg": ps["deg"], "niter": ps["niter"],
-                         "npolish": ps["npolish"], "status": ps["status"],
+            res_[prec] = r
+            rec[prec] = {"nev": r["nev"], "s": dt, "eigenpairs_per_s": r["nev"] / dt,
+                         "degrees": [p["deg"] for p in r["per_slice"]],
+                         "niter": [p["niter"] for p in r["per_slice"]],
+                         "fp64_phase": [p["npolish"] for p in r["per_slice"]],
+                         "status": [p["status"] for p in r["per_slice"]],
                          "max_residual": float(r["res"].max()) if r["nev"] else None}
-            print(f"[precision] {iv} {prec}: {r['nev']} pairs, degree {ps['deg']}, {dt:.1f} s",
-                  file=sys.stderr, flush=True)
-        l64, l32 = np.sort(lams["f64"]), np.sort(lams["f32"])
-        normA = max(abs(r["bounds"][0]), abs(r["bounds"][1]))
-        if len(l64) == len(l32) and len(l64):
-            err = np.abs(l32 - l64) / normA
-            rec["f32_vs_f64_eig_err"] = {"max": float(err.max()), "median": float(np.median(err))}
+            print(f"[precision] {name} {prec}: {r['nev']} pairs in {dt:.1f} s, status "
+                  f"{rec[prec]['status']}", file=sys.stderr, flush=True)
+        l64, l32 = np.sort(res_["f64"]["lam"]), np.sort(res_["f32"]["lam"])
+        pairs, miss, extra = match_eigs(l64, l32)
+        err = np.array([abs(l32[j] - l64[k]) / abs(l64[k]) for k, j in pairs])
+        rec["f32_vs_f64"] = {"matched": len(pairs), "missing_in_f32": [float(l64[k]) for k in miss],
+                             "extra_in_f32": [float(l32[j]) for j in extra],
+                             "rel_err_max": float(err.max()) if len(err) else None,
+                             "rel_err_median": float(np.median(err)) if len(err) else None}
+        for k, j in pairs:
+            table.append((name, "gpu-f64", l64[k], l32[j], abs(l32[j] - l64[k]) / abs(l64[k])))
+        for k in miss:
+            table.append((name, "gpu-f64", l64[k], float("nan"), float("nan")))
+        if ns == 10:
+            # slices the oracle solved: every eigenvalue of the slice against it
+            sli = res_["f32"]["slices"]
+            for q, g in sorted(gold["solved"].items()):
+                q = int(q)
+                lo_, hi_ = g["interval"]
+                ref = np.array(g["eigenvalues"])
+                if abs(sli[q] - lo_) > 1e-9 or abs(sli[q + 1] - hi_) > 1e-9:
+                    rec[f"oracle_slice_{q}"] = "slice ends differ from the oracle's; skipped"
+                    continue
+                last = q == ns - 1
+                got = l32[(l32 >= lo_) & ((l32 < hi_) | last)]
+                pr, ms, ex = match_eigs(ref, got)
+                e = np.array([abs(got[j] - ref[k]) / abs(ref[k]) for k, j in pr])
+                rec[f"f32_vs_oracle_slice_{q}"] = {
+                    "oracle_count": len(ref), "f32_count": len(got),
+                    "missing_in_f32": [float(ref[k]) for k in ms],
+                    "rel_err_max": float(e.max()) if len(e) else None}
+                for k, j in pr:
+                    table.append((f"{name}, slice {q}", "oracle", ref[k], got[j],
+                                  abs(got[j] - ref[k]) / abs(ref[k])))
+                for k in ms:
+                    table.append((f"{name}, slice {q}", "oracle", ref[k], float("nan"),
+                                  float("nan")))
         rec["speedup_f32"] = rec["f64"]["s"] / rec["f32"]["s"]
         out.append(rec)
+    if args.precision_out:
+        import csv
+        with open(args.precision_out, "w", newline="") as f:
+            wr = csv.writer(f)
+            wr.writerow(["workload", "reference", "lambda_ref", "lambda_f32", "rel_err"])
+            for w, kind, a, b, e in table:
+                wr.writerow([w, kind, f"{a:.17g}", f"{b:.17g}", f"{e:.3e}"])
     print(json.dumps({
-        "metric": "FP32-filter precision form vs FP64: eigenpairs and per-eigenvalue error",
+        "metric": "FP32-filter precision form vs FP64: eigenpairs/s and per-eigenvalue error",
         "n_gpus": 1, "dtype": "f32-filter/f64 vs f64", "data": "synthetic",
-        "config": {"workload": (f"3-D 7-point Laplacian {args.grid}^3 + U[0,1) potential (seed 0), "
-                                f"single slices, tol {args.tol:g}")},
-        "slices": out}), flush=True)
+        "config": {"workload": (f"3-D 7-point Laplacian {args.grid}^3 + U[0,1) potential "
+                                f"(seed 0), tol {args.tol:g}, tol_lo "
+                                f"{args.tol_lo or 'default'}")},
+        "runs": out}), flush=True)
 
 
 def serve_main(args):
@@ -676,7 +905,7 @@ def serve_main(args):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    ex = S.DeviceExecutor(tol=args.tol)
+    ex = S.DeviceExecutor(tol=args.tol, prec=args.serve_prec, tol_lo=args.tol_lo)
     budget = int(args.budget_gb * 2 ** 30)
     base = S.poisson_stream(args.serve_seed, args.requests, 1.0, n_max=args.serve_nmax)
     solo = {}
@@ -720,7 +949,7 @@ def serve_main(args):
 
     reqs_by_id.update({r.rid: r for r in reqs})
     led = S.Ledger(budget, args.max_running)
-    srv = S.Server(led, ex, on_tick=tick, on_result=done)
+    srv = S.Server(led, ex, on_tick=tick, on_result=done, max_bypass=args.max_bypass)
     t0 = time.perf_counter()
     out = srv.run(reqs)
     wall = time.perf_counter() - t0
@@ -728,7 +957,8 @@ def serve_main(args):
     same = 0
     for rid, r0 in solo.items():
         r1 = out[rid]
-        eq = r0.status == r1.status == "ok" and np.array_equal(r0.moments, r1.moments)
+        eq = r0.status == r1.status and r0.status in ("ok", "partial") \
+            and np.array_equal(r0.moments, r1.moments)
         if eq and r0.kind == "eigs":
             eq = (np.array_equal(r0.lam, r1.lam) and np.array_equal(r0.res, r1.res)
                   and np.array_equal(r0.ycheck, r1.ycheck))
@@ -740,16 +970,19 @@ def serve_main(args):
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64",
+        "dtype": "f32-filter/f64" if args.serve_prec == "f32" else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"Poisson stream (seed {args.serve_seed}) of {args.requests} requests: "
                          f"2-D/3-D Laplacian + U[0,1) potential, n log-uniform in "
                          f"[1e4, {args.serve_nmax:g}], half KPM DOS (degree 100, 20 vectors), "
                          f"half eigenpair requests (count U{{50..400}} from a DOS quantile "
-                         f"U[0.05, 0.6]), FP64, tol {args.tol:g}"),
+                         f"U[0.05, 0.6]), "
+                         + ("FP32-filter phase then FP64 phase, FP64 Ritz and residuals"
+                            if args.serve_prec == "f32" else "FP64")
+                         + f", tol {args.tol:g}"),
             "rate_per_s": rate, "calibration_s": t_solo, "budget_bytes": budget,
-            "max_running": args.max_running,
+            "max_running": args.max_running, "max_bypass": args.max_bypass,
         },
         **summ,
         "device_mem_high_water_bytes": int(hw["used"]),
@@ -810,14 +1043,42 @@ def main():
     if args.precision_study:
         precision_main(args, ctx, ev, Ad, A)
         return
-    for _ in range(args.warmup):
+    if args.c3_only:
+        c3 = c3_filter_leg(ctx, ev, args, lambda m: print(m, file=sys.stderr, flush=True))
+        c3.pop("check_column", None)
+        c3.pop("A_host", None)
+        print(json.dumps({"metric": "filter SpMM HBM GB/s (algorithmic bytes)",
+                          "value": c3["roofline"]["achieved"], "unit": "GB/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": c3["workload"]}, "c3_filter": c3}), flush=True)
+        return
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    # At most one warm-up solve; then whole solves while the next one (timed
+    # like the last) still ends before the deadline, so that the run, the
+    # 200^3 filter leg and the oracle sample fit the measurement window.
+    nwarm = min(args.warmup, 1)
+    last = None
+    for _ in range(nwarm):
+        tw = time.perf_counter()
         one_step(ctx, ev, Ad, args)
+        torch.cuda.synchronize()
+        last = time.perf_counter() - tw
+        log(f"[bench] warm-up solve {last:.1f} s")
     torch.cuda.synchronize()
     ctx.reset_stats()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(max(args.steps, 1)):
+        now = time.perf_counter()
+        if i > 0 and args.time_budget > 0 and now - T_START + last > args.time_budget:
+            break
         recs.append(one_step(ctx, ev, Ad, args))
+        torch.cuda.synchronize()
+        last = time.perf_counter() - now
+        log(f"[bench] step {i}: {recs[-1]['nev']} eigenpairs in {last:.1f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fs = ctx.filter_stats()
@@ -829,7 +1090,8 @@ def main():
     per_launch_bytes = fs["bytes"] / max(fs["launches"], 1)
     solver = {"tr": "thick-restart Lanczos", "nr": "non-restart Lanczos",
               "si": "subspace iteration"}[args.method]
-    arith = ("FP32 filter + FP64 reorthogonalisation/Rayleigh-Ritz/polish" if args.prec == "f32"
+    arith = ("FP32-filter phase then FP64 phase, FP64 reorthogonalisation/Rayleigh-Ritz"
+             if args.prec == "f32"
              else "FP64")
     workload = (f"3-D 7-point Laplacian {N}^3 + U[0,1) diagonal potential (seed 0), "
                 f"all eigenpairs in [{rec['interval'][0]:.6g}, {rec['interval'][1]:.6g}]"
@@ -847,9 +1109,11 @@ def main():
         "value": value,
         "unit": "eigenpairs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": len(recs),
+        "warmup": nwarm,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "ms_per_step": elapsed / len(recs) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -889,8 +1153,18 @@ def main():
         avg_s = fs["seconds"] / fs["launches"]
         out["roofline"]["traffic"] = tb / avg_s / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = tb
+    c3 = None
+    if args.c3 and N == 100:
+        c3 = c3_filter_leg(ctx, ev, args, log)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, rec, args)
+        out["cpu_baseline"] = cpu_baseline(A, rec, args, c3)
+    if c3 is not None:
+        c3.pop("check_column", None)
+        c3.pop("A_host", None)
+        out["c3_filter"] = c3
+        out["config"]["workload"] = ("value, roofline: " + out["config"]["workload"]
+                                     + "; c3_filter: " + c3["workload"])
+    out["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 
 

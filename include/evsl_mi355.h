@@ -24,6 +24,7 @@
 #ifndef EVSL_MI355_H
 #define EVSL_MI355_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -101,8 +102,9 @@ typedef struct {
   const void *val32; /* EVSL_F32: device float values of A (NULL: the library converts A) */
   double tol_lo;  /* EVSL_F32: lock tolerance of the FP32 phase;
                      0: max(tol, min(1e-3, 2e-7 deg)) */
-  int polish;     /* EVSL_F32: max FP64 polish rounds; 0: 4; < 0: none (FP32-phase pairs) */
-  int polish_div; /* EVSL_F32: polish filter degree = deg / polish_div; 0: 1 (same filter) */
+  int polish;     /* EVSL_F32: < 0: no FP64 phase (the FP32-phase pairs are returned as they
+                     are); otherwise the FP64 phase below runs when needed */
+  int polish_div; /* unused; keep 0 */
   int method;     /* EVSL_LAN_TR (0) or EVSL_LAN_NR (FP64 only; else EVSL_ENOTIMPL) */
   int reserved;
 } evsl_lan_opts_t;
@@ -117,9 +119,16 @@ typedef struct {
  * columns plus two chunks. */
 /* Precision form (prec = EVSL_F32): the filter recurrence runs in FP32 values,
  * vectors and accumulation; reorthogonalisation, Rayleigh-Ritz, the residual
- * test and the coefficients stay FP64. Pairs are locked at tol_lo, then the
- * locked block is polished in FP64 (filter, Cholesky QR, Rayleigh-Ritz with A)
- * until every residual is <= tol. */
+ * test and the coefficients stay FP64. The FP32 phase locks pairs at tol_lo
+ * (residuals computed in FP64) and ends by the usual rule, or when two
+ * restarts in a row lock nothing while candidates remain (the FP32 floor).
+ * Pairs whose residual already meets tol are kept; when any other pair or
+ * candidate remains (or the phase hit max_its), an FP64 phase follows: the
+ * same thick-restart Lanczos with the FP64 filter, deflated against the kept
+ * pairs and started from the normalised sum of the other FP32-phase Ritz
+ * vectors, so the result is complete at tol. In a batch the FP64 phases of
+ * all slices run together after their FP32 phases. npolish reports 1 when
+ * the FP64 phase ran. */
 
 /* Result of one slice. lam/res are host arrays and Y a device n x nev
  * column-major array, all allocated by the library and released with
@@ -133,7 +142,7 @@ typedef struct {
   int niter;      /* Lanczos steps */
   int nmv;        /* products with A (filter steps + Ritz checks) */
   int nrestart;
-  int npolish;    /* FP64 polish rounds (precision form) */
+  int npolish;    /* precision form: 1 when the FP64 phase ran, else 0 */
   int status;     /* EVSL_OK or EVSL_ENOCONV */
   int north2;     /* Lanczos steps whose reorthogonalisation made a second
                      Gram-Schmidt pass (DGKS test, Section 2.3) */
@@ -143,11 +152,28 @@ typedef struct {
   double t_tot;   /* wall time of the call; in a batch, when this slice finished */
 } evsl_eigs_t;
 
+/* Device memory allocator of a context. alloc returns at least `bytes` bytes
+ * of device memory usable on `stream` (the context's hipStream_t), or NULL
+ * when it cannot: the call that asked then returns EVSL_ENOMEM with every
+ * buffer it had taken handed back to free and the context's ledger
+ * (evsl_mem_stats) where it was. free receives exactly the pointers alloc
+ * returned, once each, after the work on `stream` that uses them has been
+ * ordered before it (the library synchronises the stream before freeing
+ * workspace). `user` is passed through unchanged. */
+typedef struct {
+  void *(*alloc)(void *user, size_t bytes, void *stream);
+  void (*free)(void *user, void *ptr, void *stream);
+  void *user;
+} evsl_alloc_t;
+
 /* ---- context (replaces EVSLStart/EVSLFinish of Section 3.1) ----
- * stream: a hipStream_t (NULL = the null stream). The context holds the
- * stream, a grow-only device workspace, the tuning table and timers. Not
- * thread-safe: one context per host thread and stream. */
-int evsl_create(evsl_ctx_t *ctx, void *stream);
+ * stream: a hipStream_t (NULL = the null stream). alloc: the device allocator
+ * for every buffer the context holds (workspace, slice bases, result
+ * vectors), copied into the context; NULL = hipMalloc/hipFree; EVSL_EINVAL
+ * when given with a NULL alloc or free. The context holds the stream, a
+ * grow-only device workspace, the tuning table and timers. Not thread-safe:
+ * one context per host thread and stream. */
+int evsl_create(evsl_ctx_t *ctx, void *stream, const evsl_alloc_t *alloc);
 int evsl_destroy(evsl_ctx_t ctx);
 /* hipError_t of the last EVSL_EHIP returned by this context. */
 int evsl_last_hip_error(evsl_ctx_t ctx);
@@ -365,6 +391,29 @@ int evsl_set_spmv_variant(evsl_ctx_t ctx, int variant);
  * lane (16-byte loads) when the block allows it (default), 3 as 2 without the
  * XCD order and one column per lane, 4 as 2 with one column per lane. */
 int evsl_set_block_variant(int variant);
+/* Launch schedule of this context's block filter steps (variant 2), a choice
+ * of how workgroups walk an n x nc row-major block and so of what the caches
+ * can reuse; results are bit-identical under every schedule (each element is
+ * computed by the same arithmetic in the same order):
+ *   map 0  row blocks in launch order, all nc columns per row block;
+ *   map 1  (default) as 0 with each of the 8 XCDs sweeping a contiguous row
+ *          range;
+ *   map 2  the columns in chunks of chunk_cols, one chunk after another over
+ *          all rows; within a chunk, row blocks are dealt to the XCDs in runs
+ *          of `group` consecutive blocks, so all XCDs sweep the same rows
+ *          together while each keeps short runs of neighbouring rows.
+ * A chunk as wide as the block, or not a multiple of the lane width, falls
+ * back to map 1; so do the KPM steps. */
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group);
+int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group);
+/* Times the Clenshaw degree step of the block filter (eq:Cheb0 evaluated by
+ * Clenshaw's recurrence) on A over an n x ncols block of scratch vectors for
+ * each candidate schedule (maps 0 and 1; map 2 with chunks of 16-128 columns
+ * and runs of 1-64 row blocks), keeps the fastest in the context and
+ * returns its milliseconds per step. Uses 3 n x ncols blocks of workspace
+ * (value size by prec). Synchronous. */
+int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int prec,
+                           double *ms_per_step);
 
 #ifdef __cplusplus
 }

@@ -33,6 +33,7 @@ EXPORTS = [
     "evsl_gram", "evsl_mem_stats", "evsl_filtered_subspace", "evsl_filtered_subspace_batch",
     "evsl_set_graphs", "evsl_lanczos_dos", "evsl_lanczos_count", "evsl_slice_spectrum_lanczos",
     "evsl_lspol", "evsl_spectrum_bounds_gen", "evsl_filtered_lanczos_gen",
+    "evsl_set_block_schedule", "evsl_get_block_schedule", "evsl_autotune_schedule",
 ]
 
 
@@ -88,7 +89,7 @@ def _lib():
         L = C.CDLL(LIB_PATH)
         L.evsl_strerror.restype = C.c_char_p
         L.evsl_strerror.argtypes = [C.c_int]
-        L.evsl_create.argtypes = [C.POINTER(C.c_void_p), C.c_void_p]
+        L.evsl_create.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
         L.evsl_destroy.argtypes = [C.c_void_p]
         L.evsl_last_hip_error.argtypes = [C.c_void_p]
         L.evsl_spectrum_bounds.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_uint64, _dp, _dp]
@@ -133,6 +134,9 @@ def _lib():
         L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int,
                                     C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
+        L.evsl_set_block_schedule.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.evsl_get_block_schedule.argtypes = [C.c_void_p, _ip, _ip, _ip]
+        L.evsl_autotune_schedule.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int, _dp]
         L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
         L.evsl_filtered_subspace.argtypes = [C.c_void_p, C.POINTER(CsrT), _dp, C.POINTER(PolT),
                                              C.POINTER(SiOptsT), C.POINTER(EigsT)]
@@ -171,16 +175,39 @@ def _dptr(a):
 
 
 # ------------------------------------------------------------------ context / matrices
-class Ctx:
-    """evsl_ctx_t bound to a torch (HIP) stream."""
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
-    def __init__(self, stream=None):
+
+class AllocT(C.Structure):
+    """evsl_alloc_t: a device allocator given to evsl_create."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+def make_allocator(alloc, free):
+    """evsl_alloc_t from two Python callables: alloc(nbytes, stream) -> device
+    address (int) or 0 when it cannot; free(ptr, stream). The returned object
+    keeps the callbacks alive; pass it to Ctx(alloc=...)."""
+    a = ALLOC_FN(lambda user, nbytes, stream: alloc(int(nbytes), stream) or None)
+    f = FREE_FN(lambda user, ptr, stream: free(ptr, stream))
+    t = AllocT(a, f, None)
+    t._keep = (a, f)
+    return t
+
+
+class Ctx:
+    """evsl_ctx_t bound to a torch (HIP) stream; `alloc` an evsl_alloc_t from
+    make_allocator (None: the library's hipMalloc)."""
+
+    def __init__(self, stream=None, alloc=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.alloc = alloc
         self.h = C.c_void_p()
-        _chk(_lib().evsl_create(C.byref(self.h), C.c_void_p(stream.cuda_stream)), "evsl_create")
+        _chk(_lib().evsl_create(C.byref(self.h), C.c_void_p(stream.cuda_stream),
+                                C.byref(alloc) if alloc is not None else None), "evsl_create")
 
     def close(self):
         if self.h:
@@ -214,6 +241,17 @@ class Ctx:
     def set_group_width(self, g):
         _chk(_lib().evsl_set_group_width(self.h, int(g)), "set_group_width")
 
+    def set_block_schedule(self, map, chunk_cols=0, group=1):
+        _chk(_lib().evsl_set_block_schedule(self.h, int(map), int(chunk_cols), int(group)),
+             "evsl_set_block_schedule")
+
+    def block_schedule(self):
+        """(map, chunk columns, row-block run) of the block filter schedule."""
+        m, c, g = C.c_int(), C.c_int(), C.c_int()
+        _chk(_lib().evsl_get_block_schedule(self.h, C.byref(m), C.byref(c), C.byref(g)),
+             "evsl_get_block_schedule")
+        return m.value, c.value, g.value
+
     def mem_stats(self, reset_peak=False):
         """(bytes held now, peak bytes) of the context's device allocations."""
         cur, peak = C.c_int64(), C.c_int64()
@@ -236,6 +274,15 @@ def evsl_autotune(ctx, A, max_cols, prec=EVSL_F64):
     _chk(_lib().evsl_autotune(ctx.h, C.byref(A.t), int(max_cols), int(prec), C.byref(g),
                               C.byref(us)), "evsl_autotune")
     return g.value, us.value
+
+
+def evsl_autotune_schedule(ctx, A, ncols, prec=EVSL_F64):
+    """Picks the block filter schedule for ncols columns on A (kept in ctx);
+    returns (map, chunk columns, row-block run, ms per degree step)."""
+    ms = C.c_double()
+    _chk(_lib().evsl_autotune_schedule(ctx.h, C.byref(A.t), int(ncols), int(prec), C.byref(ms)),
+         "evsl_autotune_schedule")
+    return ctx.block_schedule() + (ms.value,)
 
 
 class DeviceCsr:
@@ -363,8 +410,7 @@ def evsl_cheb_coeffs(intv, damping=DAMP_JACKSON, tau=0.8, tau_ext=0.4, max_deg=1
     return p
 
 
-def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
-    """Y = p(A-hat) V for row-major torch tensors V, Y (n x ncols, contiguous)."""
+def _filter_call(fn, name, ctx, A, pols, col_group, V, Y, prec):
     import torch
     if prec is None:
         prec = EVSL_F64 if V.dtype == torch.float64 else EVSL_F32
@@ -372,9 +418,15 @@ def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
     ldv = 1 if V.dim() == 1 else V.stride(0)
     arr = (PolT * len(pols))(*[p.t for p in pols])
     cg = np.ascontiguousarray(col_group, dtype=np.int32)
-    _chk(_lib().evsl_filter_apply(ctx.h, C.byref(A.t), arr, len(pols),
-                                  cg.ctypes.data_as(C.POINTER(C.c_int32)), C.c_void_p(V.data_ptr()),
-                                  C.c_void_p(Y.data_ptr()), ldv, ncols, prec), "evsl_filter_apply")
+    _chk(fn(ctx.h, C.byref(A.t), arr, len(pols), cg.ctypes.data_as(C.POINTER(C.c_int32)),
+            C.c_void_p(V.data_ptr()), C.c_void_p(Y.data_ptr()), ldv, ncols, prec), name)
+
+
+def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
+    """Y = p(A-hat) V for row-major torch tensors V, Y (n x ncols, contiguous)."""
+    _filter_call(_lib().evsl_filter_apply, "evsl_filter_apply", ctx, A, pols, col_group, V, Y,
+                 prec)
+
 
 
 def lan_opts(m=0, max_its=0, ncycle=0, tol=1e-8, seed=2, nev_est=0, nev_cap=0, prec=EVSL_F64,

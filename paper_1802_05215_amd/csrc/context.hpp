@@ -36,6 +36,7 @@ struct evsl_ctx_s {
   int last_hip = 0;
   int spmv_variant = 0;  // 0 auto, 1 direct, 2 LDS-staged, 3/4 unrolled
   int group_width = 0;   // columns per block filter launch in batches (0: all)
+  evk::BlkSched blk_sched;  // block filter schedule (evsl_set_block_schedule, autotuner)
   bool timing = true;
   bool use_graphs = true;  // batch group filters replayed from HIP graphs
   hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
@@ -58,6 +59,8 @@ struct evsl_ctx_s {
   // device memory held by this context (workspace, slice buffers, results)
   std::unordered_map<void *, size_t> live;
   int64_t mem_cur = 0, mem_peak = 0;
+  // caller's device allocator (alloc == nullptr: hipMalloc / hipFree)
+  evsl_alloc_t alloc{};
 };
 
 namespace evc {
@@ -74,11 +77,16 @@ inline void hipchk(evsl_ctx_t ctx, hipError_t e) {
 inline void *dalloc(evsl_ctx_t ctx, size_t bytes) {
   void *p = nullptr;
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->last_hip = (int)e;
-    fail(EVSL_ENOMEM);
+  if (ctx->alloc.alloc) {
+    p = ctx->alloc.alloc(ctx->alloc.user, bytes, (void *)ctx->stream);
+    if (!p) fail(EVSL_ENOMEM);
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->last_hip = (int)e;
+      fail(EVSL_ENOMEM);
+    }
   }
   ctx->live[p] = bytes;
   ctx->mem_cur += (int64_t)bytes;
@@ -88,9 +96,11 @@ inline void *dalloc(evsl_ctx_t ctx, size_t bytes) {
 
 // Frees a buffer from dalloc and takes it off the context's ledger.
 inline void dfree(evsl_ctx_t ctx, void *p) {
-  if (!p) return;
-  (void)hipFree(p);
-  if (!ctx) return;
+  if (!p || !ctx) return;
+  if (ctx->alloc.alloc)
+    ctx->alloc.free(ctx->alloc.user, p, (void *)ctx->stream);
+  else
+    (void)hipFree(p);
   auto it = ctx->live.find(p);
   if (it != ctx->live.end()) {
     ctx->mem_cur -= (int64_t)it->second;

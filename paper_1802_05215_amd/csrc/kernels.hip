@@ -346,7 +346,21 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
 // products; VEC > 1 needs nc and ld divisible by VEC and VEC-aligned base
 // pointers. With DELTA the column indices come as 16-bit offsets from the row
 // (cd), half the index bytes of a matrix whose bandwidth is below 2^15.
-template <typename T, int KIND, bool XCD, int VEC, bool WIDE, bool DELTA>
+//
+// Schedule (runtime `map`; a workgroup covers rows_per_wg rows of one chunk of
+// cw columns; nrb row blocks per chunk):
+//   0  one chunk (cw = nc), row blocks in launch order;
+//   1  one chunk, row blocks renumbered so each of the 8 XCDs sweeps a
+//      contiguous row range (neighbouring rows share an L2);
+//   2  column chunks of cw columns, chunk 0 over all rows, then chunk 1, ...;
+//      within a chunk the row blocks go to the XCDs in runs of grp blocks
+//      (run j to XCD j mod 8; npad >= nrb blocks per chunk, a multiple of
+//      8 grp, the padding blocks exit at once). All XCDs then sweep the same
+//      rows of the same narrow chunk together: a row of W gathered again far
+//      away (a neighbouring plane of a 3-D stencil) is re-read while it is
+//      still in the Infinity Cache, and rows gathered from close by (the
+//      neighbouring lines) are mostly in the XCD's own L2.
+template <typename T, int KIND, int VEC, bool WIDE, bool DELTA>
 __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_per_wg,
                                                       const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
@@ -356,7 +370,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
                                                       T *Y, int64_t ld64,
                                                       const double *__restrict__ coef, int cld,
                                                       int jnext, const T *__restrict__ Vd,
-                                                      double *partial) {
+                                                      double *partial, int map, int cw, int nrb,
+                                                      int npad, int grp) {
   typedef T vt __attribute__((ext_vector_type(VEC)));
   constexpr int CAP = 1792;
   constexpr bool IS_CLEN = (KIND == STEP_CLEN);
@@ -369,7 +384,18 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
   __shared__ T s_va[CAP];
   __shared__ double red[4];
   const int tid = threadIdx.x;
-  const int bx = XCD ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int bid = blockIdx.x;
+  int bx, chunk = 0;
+  if (map == 2) {
+    const int x = bid & 7, local = bid >> 3, per = npad >> 3;
+    chunk = local / per;
+    const int lc = local - chunk * per;
+    bx = ((lc / grp) * 8 + x) * grp + lc % grp;
+    if (bx >= nrb) return;  // padding block (uniform over the workgroup)
+  } else {
+    bx = map == 1 ? xcd_remap(bid, gridDim.x) : bid;
+  }
+  const int cbase = chunk * cw;  // first column of the chunk
   const int r0 = bx * rows_per_wg;
   const int nr = min(rows_per_wg, n - r0);
   for (int i = tid; i <= nr; i += TPB) s_rp[i] = rp[r0 + i];
@@ -384,7 +410,7 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
     }
   }
   __syncthreads();
-  const int ncv = nc / VEC;  // vector slots per row
+  const int ncv = cw / VEC;  // vector slots per row of the chunk
   int R0, rsub, slot;
   bool active;
   if (ncv <= TPB) {
@@ -398,7 +424,8 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
     slot = blockIdx.y * TPB + tid;
     active = slot < ncv;
   }
-  const int col = slot * VEC;
+  const int col = cbase + slot * VEC;
+  active = active && col < nc;
   const int ld = (int)ld64;
   // offset of element (row, 0) of the block
   auto roff = [&](int row) -> size_t {
@@ -416,6 +443,14 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
     for (int rl = rsub; rl < nr; rl += R0) {
       const int kb = s_rp[rl] - nz0, ke = s_rp[rl + 1] - nz0;
       const int row = r0 + rl;
+      const size_t e = roff(row) + col;
+      // the row's own operands are loaded first, so that their loads are in
+      // flight together with the gathers below (Wn may alias Wp, but only
+      // element e, which this thread reads before it writes)
+      const vt w = *(const vt *)(W + e);
+      const vt wp = HAS_PREV ? *(const vt *)(Wp + e) : (vt)(T)0;
+      const vt vd = (IS_CLEN || HAS_DOT) ? *(const vt *)(Vd + e) : (vt)(T)0;
+      const vt yo = (HAS_Y && !Y_INIT) ? *(const vt *)(Y + e) : (vt)(T)0;
       vt acc = (T)0;
       if (staged) {
         for (int k = kb; k < ke; k += 8) {
@@ -435,18 +470,15 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
         for (int k = kb + nz0; k < ke + nz0; ++k)
           acc += va[k] * *(const vt *)(wc + roff(DELTA ? row + (int)cd[k] : ci[k]));
       }
-      const size_t e = roff(row) + col;
-      const vt w = *(const vt *)(W + e);
       vt wn = s1 * acc + s0 * w;
-      if (HAS_PREV) wn -= *(const vt *)(Wp + e);
-      if (IS_CLEN) wn += c1 * *(const vt *)(Vd + e);
+      if (HAS_PREV) wn -= wp;
+      if (IS_CLEN) wn += c1 * vd;
       *(vt *)(Wn + e) = wn;
       if (HAS_Y) {
-        const vt y = Y_INIT ? c0 * w : *(const vt *)(Y + e);
+        const vt y = Y_INIT ? c0 * w : yo;
         *(vt *)(Y + e) = y + c1 * wn;
       }
       if (HAS_DOT) {
-        const vt vd = *(const vt *)(Vd + e);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) dacc += (double)vd[v] * (double)wn[v];
       }
@@ -458,13 +490,15 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
   }
 }
 
-static int g_blk_variant = 2;  // 1: global loads, 2: LDS + XCD remap, 3: LDS, 4: 2 as VEC 1
+// 1: global loads; 2: LDS-staged, 16-byte lanes, scheduled; 3: LDS-staged,
+// one column per lane, launch order; 4: 2 with one column per lane
+static int g_blk_variant = 2;
 
 void set_blk_variant(int v) { g_blk_variant = (v >= 1 && v <= 4) ? v : 2; }
 
 // Columns per lane for a launch: 2 (16-byte loads) when the block allows it.
 static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int np) {
-  if (g_blk_variant == 4 || g_blk_variant == 1) return 1;
+  if (g_blk_variant != 2) return 1;
   int v = es == 8 ? 2 : 4;  // 16-byte loads
   while (v > 1) {
     bool ok = (nc % v == 0) && (ld % v == 0);
@@ -476,6 +510,7 @@ static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int n
   return v;
 }
 
+// Rows per workgroup and grid for nc columns (one chunk of cw = nc columns).
 static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid) {
   const int ncv = nc / vec;
   const int R0 = ncv <= TPB ? TPB / ncv : 1;
@@ -495,10 +530,32 @@ int blk_partials(int n, int nc) {
   return (int)(g.x * g.y);
 }
 
+// The schedule actually used for a launch: map 2 needs a chunk width that is
+// a multiple of VEC with at most 256 slots and below nc, and grp >= 1;
+// otherwise (and for the KPM kinds, whose partial sums are indexed by
+// workgroup) the launch is one chunk with contiguous row ranges per XCD.
+static BlkSched blk_resolve(const BlkSched *sc, int nc, int vec, int kind) {
+  BlkSched r;
+  r.map = g_blk_variant == 3 ? 0 : 1;
+  r.cw = nc;
+  r.grp = 1;
+  if (!sc || g_blk_variant == 3 || kind == STEP_KPM_FIRST || kind == STEP_KPM_NEXT) return r;
+  if (sc->map == 0 || sc->map == 1) {
+    r.map = sc->map;
+    return r;
+  }
+  const int cw = sc->cw;
+  if (cw < vec || cw % vec || cw / vec > TPB || cw >= nc || sc->grp < 1) return r;
+  r.map = 2;
+  r.cw = cw;
+  r.grp = sc->grp;
+  return r;
+}
+
 template <typename T>
 void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const T *W,
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
-              const T *Vd, double *partial) {
+              const T *Vd, double *partial, const BlkSched *sched) {
   if (A.n <= 0 || nc <= 0) return;
   const bool wide = (int64_t)A.n * ld >= ((int64_t)1 << 31);
   const bool ok32 = ld < ((int64_t)1 << 31) && (int64_t)A.n < ((int64_t)1 << 31) &&
@@ -506,26 +563,33 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
   const int var = ok32 ? g_blk_variant : 1;
   const void *ptrs[5] = {W, Wp, Wn, Y, Vd};
   const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5);
+  // the global-load kernel (variant 1) takes no schedule: one chunk
+  const BlkSched sc = var == 1 ? BlkSched{0, nc, 1} : blk_resolve(sched, nc, vec, kind);
   int rpw;
   dim3 grid;
-  blk_shape(A.n, nc, vec, &rpw, &grid);
+  blk_shape(A.n, sc.cw, vec, &rpw, &grid);
+  const int nrb = (int)grid.x;
+  int npad = nrb;
+  if (sc.map == 2) {
+    const int run = 8 * sc.grp;
+    npad = (nrb + run - 1) / run * run;
+    grid.x = (unsigned)((int64_t)npad * ((nc + sc.cw - 1) / sc.cw));
+  }
   const T *va = (const T *)A.va;
 #define EVK_BLK_ARGS                                                                          \
   grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld, coef, cld, \
       jnext, Vd, partial
 #define EVK_LDS_ARGS                                                                          \
   grid, dim3(TPB), 0, s, A.n, nc, rpw, A.rp, A.ci, A.cd, va, (T)s1, (T)s0, W, Wp, Wn, Y, ld,    \
-      coef, cld, jnext, Vd, partial
+      coef, cld, jnext, Vd, partial, sc.map, sc.cw, nrb, npad, sc.grp
 #define EVK_LAUNCH_LDS(K, W, D)                                                              \
   do {                                                                                       \
-    if (var == 3)                                                                            \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, false, 1, W, D>), EVK_LDS_ARGS);              \
-    else if (vec == 4)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 4, W, D>), EVK_LDS_ARGS);               \
+    if (vec == 4)                                                                            \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, 4, W, D>), EVK_LDS_ARGS);                     \
     else if (vec == 2)                                                                       \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 2, W, D>), EVK_LDS_ARGS);               \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, 2, W, D>), EVK_LDS_ARGS);                     \
     else                                                                                     \
-      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, true, 1, W, D>), EVK_LDS_ARGS);               \
+      hipLaunchKernelGGL((k_cheb_blk_lds<T, K, 1, W, D>), EVK_LDS_ARGS);                     \
   } while (0)
 #define EVK_LAUNCH_BLK(K)                                                                    \
   do {                                                                                       \
@@ -556,10 +620,10 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
 
 template void cheb_blk<double>(hipStream_t, const Csr &, int, double, double, const double *,
                                const double *, double *, double *, int64_t, int, const double *,
-                               int, int, const double *, double *);
+                               int, int, const double *, double *, const BlkSched *);
 template void cheb_blk<float>(hipStream_t, const Csr &, int, double, double, const float *,
                               const float *, float *, float *, int64_t, int, const double *, int,
-                              int, const float *, double *);
+                              int, const float *, double *, const BlkSched *);
 
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_fill_zero(int64_t count, T *p) {

@@ -46,13 +46,23 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
               const T *W, const T *Wp, T *Wn, T *Y, int64_t ld, int ncol, const double *coef,
               int cld, int jnext, const T *Vd = nullptr);
 
+// Launch schedule of the block filter (see k_cheb_blk_lds): map 0 launch
+// order, 1 contiguous row ranges per XCD, 2 column chunks of cw columns one
+// after another with row blocks dealt to the XCDs in runs of grp.
+struct BlkSched {
+  int map = 1;
+  int cw = 0;
+  int grp = 1;
+};
+
 // Row-major block n x ld, first nc columns active. For the KPM kinds, Vd is
 // the probe block and partial receives one partial sum of Vd . Wn per
-// workgroup (partial must hold blk_partials(n, nc) doubles).
+// workgroup (partial must hold blk_partials(n, nc) doubles). sched: null =
+// one chunk with contiguous row ranges per XCD (map 1).
 template <typename T>
 void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const T *W,
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
-              const T *Vd, double *partial);
+              const T *Vd, double *partial, const BlkSched *sched = nullptr);
 int blk_partials(int n, int nc);
 // Block kernel choice: 1 global loads, 2 LDS-staged + XCD remap (default), 3 LDS-staged.
 void set_blk_variant(int v);

@@ -24,6 +24,7 @@ using namespace evc;
 
 namespace {
 
+
 // --------------------------------------------------------------------------
 // Orthogonalisation helpers on a column-major basis B (n x *, leading dim ld).
 struct OrthWork {
@@ -106,7 +107,9 @@ struct Slice {
   bool nr = false;
   int lock_off = 0, cmax = 0;
   double tol_lo = 0.0;
-  int polish_max = 0, polish_div = 1, npolish = 0, nguard = 0, nstall = 0;
+  // polish_max < 0: no FP64 phase; npolish: 1 once the FP64 phase has started
+  int polish_max = 0, npolish = 0, nguard = 0, nstall = 0;
+  bool fp64_phase = false;
   const float *val32 = nullptr;
   float *own32 = nullptr, *q32 = nullptr, *w0f = nullptr, *w1f = nullptr, *zf = nullptr;
   // device buffers
@@ -217,8 +220,7 @@ struct Slice {
       // vector, which bounds what the FP32 phase can reach
       tol_lo = (opt && opt->tol_lo > 0) ? opt->tol_lo
                                         : std::max(tol, std::min(1e-3, 2e-7 * (double)deg));
-      polish_max = (opt && opt->polish != 0) ? std::max(opt->polish, 0) : 4;
-      polish_div = (opt && opt->polish_div > 0) ? opt->polish_div : 1;
+      polish_max = (opt && opt->polish < 0) ? -1 : 1;
     }
     // device memory
     ld = ((int64_t)n + 63) / 64 * 64;
@@ -282,6 +284,13 @@ struct Slice {
   // orthogonalisation relative to before (0 when it vanished). Synchronous.
   double fresh_vector(int nb, double *dst) {
     evk::lanczos_start(st(), n, seed, nrand++, z);
+    return orth_into(nb, dst);
+  }
+
+  // z orthogonalised (twice) against the first nb columns of B and normalised
+  // into dst; returns its norm after relative to before (0: it vanished).
+  // Synchronous.
+  double orth_into(int nb, double *dst) {
     evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2 + 1);
     cgs2(st(), n, nb, B, ld, z, ow);
     cgs2(st(), n, nb, B, ld, z, ow);
@@ -707,7 +716,7 @@ struct Slice {
       l = (int)tr_sel.size();
       // FP32 phase: two restarts in a row that lock nothing while candidates
       // remain mean the rest is at the FP32 floor; the thick-restart vectors
-      // (already placed after the locked ones) go to the FP64 polish
+      // (already placed after the locked ones) seed the FP64 phase
       if (prec == EVSL_F32) {
         nstall = lock_sel.empty() ? nstall + 1 : 0;
         if (nstall >= 2 && l > 0) {
@@ -736,207 +745,80 @@ struct Slice {
     }
   }
 
-  // FP64 polish of the pairs locked by the FP32 phase. Each round applies the
-  // FP64 filter to the block U of locked vectors, orthogonalises Y = p(A-hat) U
-  // against U (block classical Gram-Schmidt, twice), orthonormalises what is
-  // left through the eigen-decomposition of its Gram matrix (directions with
-  // negligible weight dropped), and runs Rayleigh-Ritz with A itself on
-  // S = [U, Y]. The filtered residual p u - theta u of a locked vector points
-  // along its error (every error direction outside the slice has nearly the
-  // same filter value), so the enlarged space removes the FP32 error that
-  // subspace iteration alone would keep. The pairs inside the slice are kept;
-  // rounds repeat until every residual is <= tol. Synchronous.
-  void polish() {
-    int P = nlock + nguard;
-    if (P == 0 || polish_max <= 0) return;
-    // the lock residuals are FP64 (FP64 products with A on the FP64 Ritz
-    // vectors): pairs locked at tol already meet it, and need no FP64 round
-    if (nguard == 0 && !res.empty() && *std::max_element(res.begin(), res.end()) <= tol) return;
+  // Precision form, second phase (the FP64 continuation). The FP32-filter
+  // phase ends with pairs locked at tol_lo and, when it stalled, a
+  // thick-restart set; their residuals are FP64 (FP64 products with A on FP64
+  // Ritz vectors). Pairs that already meet tol stay locked. Every other Ritz
+  // vector of the FP32 phase is accurate to about the FP32 filter's floor, so
+  // their normalised sum lies almost entirely in the wanted invariant
+  // subspace: it starts a thick-restart Lanczos run with the FP64 filter,
+  // deflated against the kept pairs, which then runs to the FP64 tolerance
+  // with the ordinary stopping rule, so no eigenpair of the slice is lost.
+  // Returns false (nothing to do) when the FP32 phase ended cleanly with every
+  // pair at tol, or when the FP64 phase is switched off (polish < 0).
+  bool begin_fp64_phase() {
+    if (prec != EVSL_F32 || fp64_phase || polish_max < 0) return false;
     hipStream_t s = st();
-    const evk::Csr Ac = to_csr(A);
-    const int dp = polish_div <= 1 ? deg : std::max(2, deg / polish_div);
-    std::vector<double> cp(dp + 1);
-    if (polish_div <= 1)
-      cp.assign(coef.begin(), coef.end());
-    else
-      evh::delta_filter(dp, gamma, 2, cp.data());
-    const int P0 = P, S2 = 2 * P0;
-    const size_t colb = sizeof(double) * ld * P0;
-    double *X0 = (double *)ws(ctx, 50, colb), *X1 = (double *)ws(ctx, 51, colb);
-    double *Yb = (double *)ws(ctx, 52, colb);
-    double *Sm = (double *)ws(ctx, 53, 2 * colb), *AS = (double *)ws(ctx, 54, 2 * colb);
-    double *Gd = (double *)ws(ctx, 55, sizeof(double) * (size_t)S2 * S2);
-    double *tnp = (double *)ws(ctx, 56, sizeof(double) * evk::gemm_tn_partials_bound(n, S2, S2));
-    double **pp = (double **)ws(ctx, 57, sizeof(double *) * 2 * P0);
-    double *ctab = (double *)ws(ctx, 58, sizeof(double) * (size_t)P0 * (dp + 1));
-    double *sc = (double *)ws(ctx, 59, sizeof(double) * 3 * S2);
-    double *Yq = Sm + (int64_t)P0 * ld;  // the second block of S
-    std::vector<double> tab((size_t)P0 * (dp + 1));
-    for (int c = 0; c < P0; ++c) std::copy(cp.begin(), cp.end(), tab.begin() + (size_t)c * (dp + 1));
-    HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
-    std::vector<double> G((size_t)S2 * S2), V((size_t)S2 * S2), w(S2), hres(3 * S2);
-    for (int round = 0; round < polish_max; ++round) {
-      npolish++;
-      // S[:, 0:P] = U; Y = p(A-hat) U (row-major block filter) into S[:, P:2P]
-      HC(ctx, hipMemcpyAsync(Sm, B, sizeof(double) * ld * P, hipMemcpyDeviceToDevice, s));
-      std::vector<const double *> hp(2 * P);
-      for (int c = 0; c < P; ++c) {
-        hp[c] = col(c);
-        hp[P + c] = Sm + (int64_t)(P + c) * ld;
-      }
-      HC(ctx, hipMemcpyAsync(pp, hp.data(), sizeof(double *) * 2 * P, hipMemcpyHostToDevice, s));
-      evk::gather_cols<double>(s, n, P, (const double *const *)pp, X0, P);
-      FilterTimer tm(ctx);
-      evk::cheb_blk<double>(s, Ac, evk::STEP_FIRST, 1.0 / dd, -cc / dd, X0, nullptr, X1, Yb, P, P,
-                            ctab, dp + 1, 1, nullptr, nullptr);
-      double *wprev = X0, *wcur = X1;
-      for (int j = 1; j < dp; ++j) {
-        evk::cheb_blk<double>(s, Ac, evk::STEP_NEXT, 2.0 / dd, -2.0 * cc / dd, wcur, wprev, wprev,
-                              Yb, P, P, ctab, dp + 1, j + 1, nullptr, nullptr);
-        std::swap(wprev, wcur);
-      }
-      tm.stop(dp, step_bytes(A, P, 8, 3) + (dp - 1) * step_bytes(A, P, 8, 5));
-      nmv += P * dp;
-      Yq = Sm + (int64_t)P * ld;
-      evk::scatter_cols<double>(s, n, P, Yb, P, (double *const *)(pp + P));
-      // First polish round: S = [U, Z] with Z an orthonormal basis of (I - U U^T) p(A) U
-      // (directions negligible against |p(A) U| dropped: they carry only
-      // rounding). Later rounds: S = an orthonormal basis of p(A) U alone
-      // (filtered subspace iteration): once U is accurate, the projected-out
-      // part of p(A) U is mostly rounding, whose Ritz values could pollute the
-      // wanted ones.
-      double *S0 = Sm;
-      int ns = 0;
-      if (round == 0) {
-        evk::col_dots(s, n, P, Yq, ld, Yq, ld, ow.partial, sc);
-        std::vector<double> yn(P);
-        HC(ctx, hipMemcpyAsync(yn.data(), sc, sizeof(double) * P, hipMemcpyDeviceToHost, s));
-        for (int t = 0; t < 2; ++t) project_out(Sm, P, Yq, P, Gd, tnp, AS);
-        HC(ctx, hipStreamSynchronize(s));
-        double ymax = 0.0;
-        for (double v : yn) ymax = std::max(ymax, v);
-        int kz = svqb(Yq, P, 1e-16 * ymax, Gd, tnp, AS, G, V, w);
-        if (kz > 0) {  // second pass against U, then normalise again
-          project_out(Sm, P, Yq, kz, Gd, tnp, AS);
-          kz = svqb(Yq, kz, 0.0, Gd, tnp, AS, G, V, w);
-        }
-        ns = P + kz;
-      } else {
-        S0 = Yq;
-        ns = svqb(Yq, P, 0.0, Gd, tnp, AS, G, V, w);
-      }
-      const int kz = ns - (S0 == Sm ? P : 0);
-      // Rayleigh-Ritz with A on S (ns columns)
-      evk::cheb_vec<double>(s, Ac, 1, evk::STEP_PLAIN, 1.0, 0.0, S0, nullptr, AS, nullptr, ld, ns,
-                            nullptr, 0, 0);
-      nmv += ns;
-      evk::gemm_tn(s, n, ns, ns, S0, ld, AS, ld, Gd, ns, tnp);
-      HC(ctx, hipMemcpyAsync(G.data(), Gd, sizeof(double) * ns * ns, hipMemcpyDeviceToHost, s));
-      HC(ctx, hipStreamSynchronize(s));
-      for (int a = 0; a < ns; ++a)
-        for (int b = 0; b < a; ++b) {
-          const double v = 0.5 * (G[a + (size_t)b * ns] + G[b + (size_t)a * ns]);
-          G[a + (size_t)b * ns] = G[b + (size_t)a * ns] = v;
-        }
-      evh::sym_eig(ns, G.data(), w.data(), V.data());
-      // all ns Ritz pairs, their Rayleigh quotients and residuals
-      double *Ua = (double *)ws(ctx, 61, sizeof(double) * ld * ns);
-      double *AUa = (double *)ws(ctx, 62, sizeof(double) * ld * ns);
-      double *sca = (double *)ws(ctx, 63, sizeof(double) * 3 * ns);
-      double *pa = (double *)ws(ctx, 64, sizeof(double) * evk::dot_partials(n, ns));
-      HC(ctx, hipMemcpyAsync(Gd, V.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice, s));
-      evk::gemm_nn(s, n, ns, ns, S0, ld, Gd, ns, Ua, ld);
-      evk::gemm_nn(s, n, ns, ns, AS, ld, Gd, ns, AUa, ld);
-      evk::col_dots(s, n, ns, Ua, ld, Ua, ld, pa, sca);
-      evk::col_dots(s, n, ns, Ua, ld, AUa, ld, pa, sca + ns);
-      evk::col_resid2(s, n, ns, Ua, AUa, ld, sca + ns, sca, pa, sca + 2 * ns);
-      std::vector<double> ha(3 * ns);
-      HC(ctx, hipMemcpyAsync(ha.data(), sca, sizeof(double) * 3 * ns, hipMemcpyDeviceToHost, s));
-      HC(ctx, hipStreamSynchronize(s));
-      // keep the pairs inside the slice: the P_in with the smallest residuals
-      // (P_in = pairs held before this round), plus any further converged one;
-      // the enlarged space also produces spurious Ritz values inside the slice,
-      // whose residuals are large
-      std::vector<int> in;
-      std::vector<double> rq(ns), rs(ns);
-      for (int c = 0; c < ns; ++c) {
-        rq[c] = ha[ns + c] / ha[c];
-        rs[c] = std::sqrt(std::max(ha[2 * ns + c], 0.0) / ha[c]) / normA;
-        if (rq[c] >= tlo && rq[c] <= thi) in.push_back(c);
-      }
-      std::stable_sort(in.begin(), in.end(), [&](int x, int y) { return rs[x] < rs[y]; });
-      std::vector<int> keep;
-      for (size_t t = 0; t < in.size(); ++t)
-        if ((int)t < P || rs[in[t]] <= tol) keep.push_back(in[t]);
-      std::sort(keep.begin(), keep.end());  // ascending eigenvalue order
-      const int k = (int)keep.size();
-      if (k > P0) {
-        status = EVSL_ENOCONV;
-        return;
-      }
-      for (int t = 0; t < k; ++t)
-        HC(ctx, hipMemcpyAsync(col(t), Ua + (int64_t)keep[t] * ld, sizeof(double) * n,
+    std::vector<int> good, bad;
+    for (int j = 0; j < nlock; ++j) (res[j] <= tol ? good : bad).push_back(j);
+    const int ng = nguard;
+    if (bad.empty() && ng == 0 && status == EVSL_OK) return false;
+    const int kw = std::min((int)bad.size() + ng, m);
+    // the warm vectors leave the basis: copy them out, then compact the kept pairs
+    double *W = (double *)ws(ctx, 40, sizeof(double) * ld * std::max(kw, 1));
+    int t = 0;
+    for (size_t q = 0; q < bad.size() && t < kw; ++q, ++t)
+      HC(ctx, hipMemcpyAsync(W + (int64_t)t * ld, col(bad[q]), sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, s));
+    for (int q = 0; q < ng && t < kw; ++q, ++t)
+      HC(ctx, hipMemcpyAsync(W + (int64_t)t * ld, col(nlock + q), sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, s));
+    std::vector<double> glam, gres;
+    for (size_t q = 0; q < good.size(); ++q) {
+      if ((int)q != good[q])
+        HC(ctx, hipMemcpyAsync(col((int)q), col(good[q]), sizeof(double) * n,
                                hipMemcpyDeviceToDevice, s));
-      double worst = 0.0;
-      int nbad = 0;
-      lam.assign(k, 0.0);
-      res.assign(k, 0.0);
-      for (int t = 0; t < k; ++t) {
-        lam[t] = rq[keep[t]];
-        res[t] = rs[keep[t]];
-        worst = std::max(worst, res[t]);
-        nbad += res[t] > tol;
-      }
-      nlock = k;
-      nguard = 0;
-      P = k;
-      if (std::getenv("EVSL_PROGRESS"))
-        std::fprintf(stderr,
-                     "[evsl] polish round %d: %d + %d columns, %d in the slice, %d above tol, "
-                     "worst %.2e\n",
-                     round + 1, ns - kz, kz, k, nbad, worst);
-      if (worst <= tol || k == 0) {
-        if (status == EVSL_ENOCONV && its <= max_its) status = EVSL_OK;
-        return;
-      }
+      glam.push_back(lam[good[q]]);
+      gres.push_back(res[good[q]]);
     }
-    status = EVSL_ENOCONV;
-  }
-
-  // Y (ny columns) <- Y - U (U^T Y) for the first nu columns U of Sm.
-  void project_out(const double *U, int nu, double *Yc, int ny, double *Gd, double *tnp,
-                   double *tmp) {
-    evk::gemm_tn(st(), n, nu, ny, U, ld, Yc, ld, Gd, nu, tnp);
-    evk::gemm_nn(st(), n, nu, ny, U, ld, Gd, nu, tmp, ld);
-    evk::axpy(st(), (int64_t)ld * ny, -1.0, tmp, Yc);
-  }
-
-  // Orthonormalise the ny columns of Y in place from the eigen-decomposition
-  // of Y^T Y = V diag(w) V^T: Y <- Y V_k diag(w_k)^(-1/2) over the eigenvalues
-  // above max(floor, 1e-20 max w). Returns the number of columns kept.
-  int svqb(double *Yc, int ny, double floor, double *Gd, double *tnp, double *tmp,
-           std::vector<double> &G, std::vector<double> &V, std::vector<double> &w) {
-    hipStream_t s = st();
-    evk::gemm_tn(s, n, ny, ny, Yc, ld, Yc, ld, Gd, ny, tnp);
-    HC(ctx, hipMemcpyAsync(G.data(), Gd, sizeof(double) * ny * ny, hipMemcpyDeviceToHost, s));
-    HC(ctx, hipStreamSynchronize(s));
-    evh::sym_eig(ny, G.data(), w.data(), V.data());
-    const double wmax = std::max(w[ny - 1], 0.0);
-    const double cut = std::max(floor, 1e-20 * wmax);
-    std::vector<double> Vk((size_t)ny * ny);
-    int k = 0;
-    for (int c = ny - 1; c >= 0; --c) {
-      if (!(w[c] > cut)) break;
-      const double sd = 1.0 / std::sqrt(w[c]);
-      for (int r = 0; r < ny; ++r) Vk[r + (size_t)k * ny] = V[r + (size_t)c * ny] * sd;
-      k++;
+    lam.swap(glam);
+    res.swap(gres);
+    nlock = (int)good.size();
+    double ok = 0.0;
+    if (kw > 0) {
+      std::vector<double> ones(kw, 1.0);
+      HC(ctx, hipMemcpyAsync(ow.h1, ones.data(), sizeof(double) * kw, hipMemcpyHostToDevice, s));
+      evk::gemm_nn(s, n, kw, 1, W, ld, ow.h1, kw, z, ld);
+      ok = orth_into(nlock, col(nlock));
     }
-    if (k == 0) return 0;
-    HC(ctx, hipMemcpyAsync(Gd, Vk.data(), sizeof(double) * ny * k, hipMemcpyHostToDevice, s));
-    evk::gemm_nn(s, n, ny, k, Yc, ld, Gd, ny, tmp, ld);
-    HC(ctx, hipMemcpyAsync(Yc, tmp, sizeof(double) * ld * k, hipMemcpyDeviceToDevice, s));
-    HC(ctx, hipStreamSynchronize(s));
-    return k;
+    if (ok == 0.0 && fresh_vector(nlock, col(nlock)) == 0.0) {
+      done = true;
+      return false;
+    }
+    // switch the filter to FP64 and restart the Lanczos state
+    prec = EVSL_F64;
+    fp64_phase = true;
+    npolish = 1;
+    if (!qin) qin = (double *)dalloc(ctx, sizeof(double) * ld);
+    if (fgx) (void)hipGraphExecDestroy(fgx);
+    if (fg) (void)hipGraphDestroy(fg);
+    fgx = nullptr;
+    fg = nullptr;
+    fg_var = -1;
+    l = 0;
+    i = 0;
+    std::fill(alpha.begin(), alpha.end(), 0.0);
+    std::fill(beta.begin(), beta.end(), 0.0);
+    th_tr.clear();
+    s_tr.clear();
+    arrow_ok = false;
+    t_old = t_new = NAN;
+    nocand = nstall = nguard = 0;
+    next_ok = true;
+    status = EVSL_OK;
+    done = false;
+    max_its = its + std::max(20 * m, 2000);
+    return true;
   }
 
   // Copy the locked pairs, sorted by eigenvalue, into a result.
@@ -992,11 +874,13 @@ const char *evsl_strerror(int code) {
 }
 
 
-int evsl_create(evsl_ctx_t *ctx, void *stream) {
+int evsl_create(evsl_ctx_t *ctx, void *stream, const evsl_alloc_t *alloc) {
   if (!ctx) return EVSL_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return EVSL_EINVAL;
   EVSL_GUARD_BEGIN
   evsl_ctx_s *c = new evsl_ctx_s();
   c->stream = (hipStream_t)stream;
+  if (alloc) c->alloc = *alloc;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return EVSL_EHIP;
@@ -1053,6 +937,96 @@ int evsl_set_block_variant(int variant) {
   if (variant < 1 || variant > 4) return EVSL_EINVAL;
   evk::set_blk_variant(variant);
   return EVSL_OK;
+}
+
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group) {
+  if (!ctx || map < 0 || map > 2 || (map == 2 && (chunk_cols < 1 || group < 1))) return EVSL_EINVAL;
+  ctx->blk_sched.map = map;
+  ctx->blk_sched.cw = map == 2 ? chunk_cols : 0;
+  ctx->blk_sched.grp = map == 2 ? group : 1;
+  return EVSL_OK;
+}
+
+int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group) {
+  if (!ctx) return EVSL_EINVAL;
+  if (map) *map = ctx->blk_sched.map;
+  if (chunk_cols) *chunk_cols = ctx->blk_sched.cw;
+  if (group) *group = ctx->blk_sched.grp;
+  return EVSL_OK;
+}
+
+int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int prec,
+                           double *ms_per_step) {
+  if (!ctx || ncols < 2 || (prec != EVSL_F64 && prec != EVSL_F32)) return EVSL_EINVAL;
+  EVSL_GUARD_BEGIN
+  check_csr(A);
+  if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
+  const int n = (int)A->n;
+  hipStream_t s = ctx->stream;
+  const size_t es = prec == EVSL_F64 ? 8 : 4;
+  const size_t blk = (size_t)n * ncols;
+  void *X0 = ws(ctx, 20, es * blk);
+  void *X1 = ws(ctx, 21, es * blk);
+  void *Yb = ws(ctx, 22, es * blk);
+  double *ctab = (double *)ws(ctx, 23, sizeof(double) * (size_t)ncols * 4);
+  evk::Csr Ac = to_csr(A);
+  attach_col_offsets(ctx, A, Ac);
+  if (prec == EVSL_F32) {
+    float *v32 = (float *)ws(ctx, 25, sizeof(float) * std::max<int64_t>(A->nnz, 1));
+    evk::to_f32(s, A->nnz, (const double *)A->val, v32);
+    Ac.va = v32;
+    Ac.dtype = EVSL_F32;
+  }
+  evk::fill_zero<double>(s, (int64_t)ncols * 4, ctab);
+  if (prec == EVSL_F32) {
+    evk::fill_zero<float>(s, (int64_t)blk, (float *)X0);
+    evk::fill_zero<float>(s, (int64_t)blk, (float *)X1);
+    evk::fill_zero<float>(s, (int64_t)blk, (float *)Yb);
+  } else {
+    evk::rademacher(s, n, ncols, 11, (double *)X0);
+    evk::rademacher(s, n, ncols, 12, (double *)X1);
+    evk::fill_zero<double>(s, (int64_t)blk, (double *)Yb);
+  }
+  // candidates: one chunk (XCD row ranges, launch order), then column chunks
+  // of 16..128 columns with row blocks dealt to the XCDs in runs of 1..64
+  std::vector<evk::BlkSched> cand;
+  cand.push_back({1, 0, 1});
+  cand.push_back({0, 0, 1});
+  for (int cw = 16; cw <= 128 && cw < ncols; cw *= 2)
+    for (int grp : {1, 4, 16, 64}) cand.push_back({2, cw, grp});
+  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+  const int reps = 4;
+  const double sc = 1e-3;  // contractive: the scratch values stay bounded
+  double best = 1e300;
+  evk::BlkSched pick = cand[0];
+  for (const evk::BlkSched &c : cand) {
+    for (int r = -1; r < reps; ++r) {
+      if (r == 0) HC(ctx, hipEventRecord(e0, s));
+      if (prec == EVSL_F32)
+        evk::cheb_blk<float>(s, Ac, evk::STEP_CLEN, sc, 0.0, (float *)X1, (float *)X0,
+                             (float *)X0, nullptr, ncols, ncols, ctab, 4, 1, (float *)Yb, nullptr,
+                             &c);
+      else
+        evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc, 0.0, (double *)X1, (double *)X0,
+                              (double *)X0, nullptr, ncols, ncols, ctab, 4, 1, (double *)Yb,
+                              nullptr, &c);
+    }
+    HC(ctx, hipEventRecord(e1, s));
+    HC(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HC(ctx, hipEventElapsedTime(&ms, e0, e1));
+    const double t = ms / reps;
+    if (t < best * 0.99) {  // keep the earlier (simpler) schedule unless clearly faster
+      best = t;
+      pick = c;
+    }
+  }
+  ctx->event_pool.push_back(e0);
+  ctx->event_pool.push_back(e1);
+  ctx->blk_sched = pick;
+  if (ms_per_step) *ms_per_step = best;
+  return EVSL_OK;
+  EVSL_GUARD_END
 }
 
 int evsl_gram(evsl_ctx_t ctx, int64_t n, int p, int q, const double *X, int64_t ldx,
@@ -1426,7 +1400,11 @@ int evsl_slice_spectrum_lanczos(const double *nodes, const double *weights, cons
              : EVSL_EINVAL;
 }
 
-int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
+namespace {
+
+// Y = p(A-hat) V (eq:Cheb0) for a block of columns with per-column filters;
+// the coefficient table and the two recurrence buffers are context workspace.
+int filter_apply_impl(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
                       const int32_t *col_group, const void *V, void *Y, int64_t ldv, int ncols,
                       int prec) {
   if (!ctx || !pols || npol < 1 || !col_group || !V || !Y || ncols < 1 || ldv < ncols ||
@@ -1466,15 +1444,17 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
       active[j] = std::max(a, 1);
     }
   hipStream_t s = ctx->stream;
-  double *ctab = (double *)ws(ctx, 10, sizeof(double) * tab.size());
-  HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+  const size_t es = prec == EVSL_F64 ? 8 : 4;
+  const size_t tab_bytes = sizeof(double) * tab.size(), blk_bytes = es * (size_t)n * ldv;
+  double *ctab = (double *)ws(ctx, 10, tab_bytes);
+  void *Wa = ws(ctx, 11, blk_bytes);
+  void *Wb = ws(ctx, 12, blk_bytes);
+  HC(ctx, hipMemcpyAsync(ctab, tab.data(), tab_bytes, hipMemcpyHostToDevice, s));
   // the table lives on this frame: wait for the upload before returning
   HC(ctx, hipStreamSynchronize(s));
-  const size_t es = prec == EVSL_F64 ? 8 : 4;
-  void *Wa = ws(ctx, 11, es * (size_t)n * ldv);
-  void *Wb = ws(ctx, 12, es * (size_t)n * ldv);
   evk::Csr Ac = to_csr(A);
   attach_col_offsets(ctx, A, Ac);
+  // the timer's events and bookkeeping are host-side; none allocates device memory
   FilterTimer tm(ctx);
   double bytes = 0.0;
   int launches = 0;
@@ -1515,7 +1495,7 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
       const double sc = k > 0 ? 2.0 : 1.0;
       T *out = k > 0 ? bk2 : y;
       evk::cheb_blk<T>(s, Ac, evk::STEP_CLEN, sc / d0, -sc * c0 / d0, bk1, bk2, out, nullptr, ldv,
-                       nc, ctab, cld, k, v, nullptr);
+                       nc, ctab, cld, k, v, nullptr, &ctx->blk_sched);
       bytes += step_bytes(A, nc, (int)es, 4);
       std::swap(bk1, bk2);
     }
@@ -1529,6 +1509,14 @@ int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
   if (hipGetLastError() != hipSuccess) return EVSL_EHIP;
   return EVSL_OK;
   EVSL_GUARD_END
+}
+
+}  // namespace
+
+int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
+                      const int32_t *col_group, const void *V, void *Y, int64_t ldv, int ncols,
+                      int prec) {
+  return filter_apply_impl(ctx, A, pols, npol, col_group, V, Y, ldv, ncols, prec);
 }
 
 int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4],
@@ -1546,13 +1534,16 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
     attach_col_offsets(ctx, A, Ac);
     sl.cd = Ac.cd;
   }
-  while (!sl.done) {
-    sl.filter_single();
-    sl.orth_and_queue();
-    HC(ctx, hipStreamSynchronize(ctx->stream));
-    sl.after_step();
+  // the precision form runs an FP64 phase after its FP32 phase
+  for (int phase = 0; phase < 2; ++phase) {
+    while (!sl.done) {
+      sl.filter_single();
+      sl.orth_and_queue();
+      HC(ctx, hipStreamSynchronize(ctx->stream));
+      sl.after_step();
+    }
+    if (phase == 0 && !sl.begin_fp64_phase()) break;
   }
-  if (sl.prec == EVSL_F32) sl.polish();
   sl.emit(out);
   out->t_tot = now_s() - t0;
   return out->status;
@@ -1573,12 +1564,12 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
   for (int q = 0; q < nslices; ++q)
     sl[q].setup(ctx, A, intv + 4 * q, &pols[q], opts ? &opts[q] : nullptr);
   const double cc = sl[0].cc, dd = sl[0].dd;
-  const int prec = sl[0].prec;
+  int prec = sl[0].prec;
   for (int q = 1; q < nslices; ++q)
     if (std::fabs(sl[q].cc - cc) > 1e-13 * (1 + std::fabs(cc)) ||
         std::fabs(sl[q].dd - dd) > 1e-13 * (1 + std::fabs(dd)) || sl[q].prec != prec)
       return EVSL_EINVAL;
-  const int es = prec == EVSL_F32 ? 4 : 8;
+  int es = prec == EVSL_F32 ? 4 : 8;
   // slices ordered by degree (non-increasing) so that the active columns of
   // the block recurrence form a prefix that shrinks as low degrees finish
   std::vector<int> order(nslices);
@@ -1635,6 +1626,20 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
     act.clear();
     for (int q : order)
       if (!sl[q].done) act.push_back(q);
+    if (act.empty() && prec == EVSL_F32) {
+      // precision form: every slice has ended its FP32 phase; those that need
+      // it continue with the FP64 filter (all active slices share one
+      // precision, so the FP64 phases run together after the FP32 ones)
+      for (int q : order)
+        if (sl[q].begin_fp64_phase()) act.push_back(q);
+      prec = EVSL_F64;
+      es = 8;
+      X0 = ws(ctx, 20, (size_t)es * n * nslices);
+      X1 = ws(ctx, 21, (size_t)es * n * nslices);
+      Yb = ws(ctx, 22, (size_t)es * n * nslices);
+      prev_act.clear();
+      graphs.clear();
+    }
     if (act.empty()) break;
     const int na = (int)act.size();
     int km = 0;
@@ -1700,7 +1705,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
           const int nck = std::min(gn, std::max(ncs[k] - g0, 1));
           const double sc = k > 0 ? 2.0 : 1.0;
           evk::cheb_blk<T>(ls, Ag, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
-                           gn, nck, gtab, km + 1, k, x0, nullptr);
+                           gn, nck, gtab, km + 1, k, x0, nullptr, &ctx->blk_sched);
           gbytes += step_bytes(A, nck, es, 4);
           std::swap(bk1, bk2);
         }
@@ -1744,10 +1749,7 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
     HC(ctx, hipStreamSynchronize(s));
     for (int q : act) {
       sl[q].after_step();
-      if (sl[q].done) {
-        if (sl[q].prec == EVSL_F32) sl[q].polish();
-        sl[q].t_done = now_s() - t0;
-      }
+      if (sl[q].done) sl[q].t_done = now_s() - t0;
     }
     ++global_step;
     if (progress > 0 && global_step % progress == 0) {

@@ -365,7 +365,7 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
     for (int k = km; k >= 0; --k) {
       const double sc = k > 0 ? 2.0 : 1.0;
       evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
-                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr);
+                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr, &ctx->blk_sched);
       bytes += step_bytes(A, ncs[k], 8, 4);
       std::swap(bk1, bk2);
     }

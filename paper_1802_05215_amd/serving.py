@@ -17,7 +17,10 @@ policy:
 * requests wait in arrival order; the head of the queue is admitted when its
   device-memory footprint (an upper bound computed from the library's own
   sizing rules) fits in the budget next to the running requests and a worker
-  slot is free; a later request never overtakes an earlier one;
+  slot is free. When the head does not fit, the earliest later request that
+  does may start instead (a bypass), at most ``max_bypass`` times per head
+  request; after that nothing overtakes it, so every request is admitted in
+  bounded time (``max_bypass = 0``: strict FIFO);
 * a request whose footprint exceeds the whole budget is rejected (status
   ``rejected``), a queued request can be cancelled until it is admitted;
 * an admitted request runs on a worker thread with its own library context
@@ -25,7 +28,10 @@ policy:
   requests; the ledger entry and the slot are returned when it finishes;
 * every kernel choice is fixed by the request alone (group width, seeds,
   slice count), and the library's reductions have a fixed order, so a
-  request computes the same bits alone or in any mix.
+  request computes the same bits alone or in any mix;
+* an eigenpair request whose slices did not all converge (a slice status
+  other than EVSL_OK) is reported as ``partial``: its pairs are returned but
+  not counted as served eigenpairs.
 
 The executor is pluggable: ``DeviceExecutor`` runs requests on the device;
 tests run the admission logic on the CPU with a simulated one.
@@ -180,7 +186,7 @@ class Result:
     arrival: float
     start: float = 0.0
     end: float = 0.0
-    status: str = "ok"            # ok | failed | rejected | cancelled
+    status: str = "ok"            # ok | partial | failed | rejected | cancelled
     nev: int = 0
     lam: Optional[np.ndarray] = None
     res: Optional[np.ndarray] = None
@@ -226,13 +232,17 @@ class Ledger:
 
 
 class Server:
-    """FIFO admission against a Ledger; one worker thread per running request."""
+    """Admission in arrival order with bounded bypass against a Ledger; one
+    worker thread per running request."""
 
     def __init__(self, ledger: Ledger, execute: Callable[[Request, float], Result],
                  clock: Callable[[], float] = time.perf_counter,
                  on_tick: Optional[Callable[[], None]] = None,
-                 on_result: Optional[Callable[[Result], None]] = None):
+                 on_result: Optional[Callable[[Result], None]] = None,
+                 max_bypass: int = 0):
         self.ledger = ledger
+        self.max_bypass = int(max_bypass)
+        self.bypassed: Dict[int, int] = {}   # head request id -> times it was passed over
         self.execute = execute
         self.clock = clock
         self.on_tick = on_tick
@@ -292,8 +302,18 @@ class Server:
                     else:
                         keep.append(r)
                 queue = keep
-                while queue and led.fits(queue[0]):
-                    req = queue.pop(0)
+                while queue:
+                    head = queue[0]
+                    if led.fits(head):
+                        req = queue.pop(0)
+                    elif self.bypassed.get(head.rid, 0) < self.max_bypass:
+                        k = next((k for k in range(1, len(queue)) if led.fits(queue[k])), 0)
+                        if k == 0:
+                            break
+                        req = queue.pop(k)
+                        self.bypassed[head.rid] = self.bypassed.get(head.rid, 0) + 1
+                    else:
+                        break
                     led.admit(req)
                     self.admission_order.append(req.rid)
                     th = threading.Thread(target=worker, args=(req,), daemon=True)
@@ -318,12 +338,19 @@ class DeviceExecutor:
     """Runs one request on the device: its own stream and library context;
     the matrix is generated on the host from the seeded input recipe and
     copied to the device; bounds, KPM, slicing, filters and the filtered
-    Lanczos of all slices run in the library, in FP64."""
+    Lanczos of all slices run in the library. prec "f32": the precision form
+    (FP32 filter phase locking at tol_lo, then the FP64 phase; Ritz,
+    reorthogonalisation and residuals FP64 throughout); "f64": FP64."""
 
-    def __init__(self, tol: float = 1e-8, group_width: int = 0, device: str = "cuda:0"):
+    def __init__(self, tol: float = 1e-8, group_width: int = 0, device: str = "cuda:0",
+                 prec: str = "f32", tol_lo: float = 0.0):
+        if prec not in ("f32", "f64"):
+            raise ValueError("prec must be f32 or f64")
         self.tol = tol
         self.group_width = group_width
         self.device = device
+        self.prec = prec
+        self.tol_lo = tol_lo
 
     def __call__(self, req: Request, t0: float) -> Result:
         import torch
@@ -370,11 +397,16 @@ class DeviceExecutor:
             ivs.append(iv)
             pols.append(ev.evsl_cheb_coeffs(iv, damping=ev.DAMP_JACKSON))
             nev_est = min(max(int(cnt * 1.3) + 5, 10), req.nev_plan)
-            opts.append(ev.lan_opts(tol=self.tol, seed=2 + q, nev_est=nev_est))
+            opts.append(ev.lan_opts(tol=self.tol, seed=2 + q, nev_est=nev_est,
+                                    prec=ev.EVSL_F32 if self.prec == "f32" else ev.EVSL_F64,
+                                    tol_lo=self.tol_lo))
         ctx.set_group_width(self.group_width)
         outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
         lams, ress, ychk = [], [], []
+        status = "ok"
         for q, (lam, Y, res, st) in enumerate(outs):
+            if st["status"] != ev.EVSL_OK:
+                status = "partial"
             # a slice that starts at the lower spectrum bound owns everything below it
             keep = ((lam >= ivs[q][0]) | (ivs[q][0] <= lo)) & ((lam < ivs[q][1]) | (q == ns - 1)) \
                 & (res <= self.tol)
@@ -383,7 +415,8 @@ class DeviceExecutor:
             if keep.any():
                 ychk.append(torch.linalg.vector_norm(Y, 1, dim=0).cpu().numpy()[keep])
         del outs
-        return Result(req.rid, "eigs", req.arrival, nev=int(sum(len(x) for x in lams)),
+        return Result(req.rid, "eigs", req.arrival, status=status,
+                      nev=int(sum(len(x) for x in lams)),
                       lam=np.concatenate(lams), res=np.concatenate(ress),
                       ycheck=np.concatenate(ychk) if ychk else np.empty(0),
                       moments=mom, interval=(xi, eta))
@@ -417,6 +450,7 @@ def summarize(results: List[Result], wall: float, ledger: Ledger) -> dict:
     return {
         "requests": len(results),
         "completed": len(ok),
+        "partial": sum(r.status == "partial" for r in results),
         "failed": sum(r.status == "failed" for r in results),
         "rejected": sum(r.status == "rejected" for r in results),
         "cancelled": sum(r.status == "cancelled" for r in results),

@@ -139,7 +139,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
 
     import paper_1802_05215_amd as pk
     mirrors = {"evsl_csr_t": pk.CsrT, "evsl_pol_t": pk.PolT, "evsl_lan_opts_t": pk.LanOptsT,
-               "evsl_si_opts_t": pk.SiOptsT, "evsl_eigs_t": pk.EigsT}
+               "evsl_si_opts_t": pk.SiOptsT, "evsl_eigs_t": pk.EigsT, "evsl_alloc_t": pk.AllocT}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "evsl_mi355.h"',
              'int main(void) {']
     for name, cls in mirrors.items():

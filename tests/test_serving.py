@@ -167,3 +167,40 @@ def test_summary_percentiles():
     assert summ["eigenpairs"] == 1000 and summ["completed"] == 100
     assert summ["latency_p50_s"] == pytest.approx(50.5)
     assert summ["latency_p99_s"] == pytest.approx(99.01)
+
+
+def test_bounded_bypass_lets_small_requests_pass_a_waiting_head():
+    """A large request at the head that does not fit next to a running one is
+    passed over by later small requests that fit, at most max_bypass times;
+    then the later requests wait until the head has started."""
+    big_run = S.Request(0, 0.0, "eigs", 3, 60, 1, target=300)
+    head = S.Request(1, 0.001, "eigs", 3, 60, 2, target=300)
+    small = [S.Request(2 + i, 0.002 + 0.0001 * i, "dos", 2, 100, 3 + i) for i in range(6)]
+    fb = S.footprint_bytes(big_run)
+    budget = int(1.5 * fb)
+    assert S.footprint_bytes(head) + fb > budget
+    assert S.footprint_bytes(small[0]) + fb <= budget
+    for max_bypass in (0, 3):
+        led = S.Ledger(budget, max_running=8)
+        ex = SimExecutor(led, scale=3e-10)
+        srv = S.Server(led, ex, max_bypass=max_bypass)
+        out = srv.run([big_run, head] + small)
+        assert all(r.status == "ok" for r in out)
+        assert led.high_water <= budget and led.used == 0
+        order = srv.admission_order
+        assert order[0] == 0
+        passed = order.index(1) - 1   # requests admitted between the first and the head
+        assert passed <= max_bypass
+        assert srv.bypassed.get(1, 0) == passed
+        if max_bypass == 0:
+            assert order == [0, 1] + [r.rid for r in small]
+        else:
+            assert passed >= 1
+
+
+def test_partial_requests_are_not_counted_as_served():
+    led = S.Ledger(10 ** 15, 2)
+    res = [S.Result(0, "eigs", 0.0, 0.0, 1.0, nev=10),
+           S.Result(1, "eigs", 0.0, 0.0, 2.0, status="partial", nev=7)]
+    summ = S.summarize(res, 10.0, led)
+    assert summ["eigenpairs"] == 10 and summ["completed"] == 1 and summ["partial"] == 1

@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--method", choices=["tr", "nr", "si"], default="tr",
                     help="slice solver: thick-restart Lanczos (default), non-restart Lanczos, "
                          "subspace iteration")
+    ap.add_argument("--si-block", type=int, default=0,
+                    help="subspace iteration: vectors per slice (0: 3 nev_est + 8)")
     ap.add_argument("--mode", choices=["batch", "serial"], default="batch",
                     help="batch: all slices in lock-step; serial: one slice after another")
     ap.add_argument("--filter-only", action="store_true",
@@ -182,7 +184,7 @@ def one_step(ctx, ev, Ad, args):
         nev_est = max(int(cnt * 1.1) + 5, 10)
         if args.method == "si":
             opts.append(ev.si_opts(tol=args.tol, seed=2 + q, nev_est=nev_est,
-                                   max_its=args.max_its))
+                                   max_its=args.max_its, block=args.si_block))
         else:
             opts.append(ev.lan_opts(tol=args.tol, seed=2 + q, nev_est=nev_est,
                                     m=int(args.m_factor * nev_est) + 30 if args.m_factor else 0,
@@ -369,9 +371,15 @@ def c3_filter_leg(ctx, ev, args, log):
         "bytes_per_step": step_bytes,
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBS, "traffic": None,
+                     "traffic_bytes_per_launch": None,
                      "kernel": "k_cheb_blk_lds<double, STEP_CLEN> at 512 columns"},
         "setup_s": t_setup,
     }
+    tb = measured_traffic(COUNTERS_C3)
+    if tb is not None and sched[:3] == (2, 64, 64):
+        # the counters were taken with this schedule
+        out["roofline"]["traffic"] = tb / (fs["seconds"] / fs["launches"]) / 1e9
+        out["roofline"]["traffic_bytes_per_launch"] = tb
     log(f"[c3] {fs['launches']} launches, {out['ms_per_launch']:.2f} ms each, {gbps:.0f} GB/s "
         f"({gbps / HBM_PEAK_GBS:.2f} of peak); degrees {min(out['slice_degrees'])}-"
         f"{max(out['slice_degrees'])}")
@@ -389,6 +397,7 @@ def c3_filter_leg(ctx, ev, args, log):
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1802_05215_amd", "csrc", "kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "filter_step_100cube_counters.txt")
+COUNTERS_C3 = os.path.join(ROOT, "profiles", "filter_block_200cube_512col_counters.txt")
 
 
 def filter_kernel_source():
@@ -401,14 +410,16 @@ def filter_kernel_source():
     return src[i:j]
 
 
-def measured_traffic():
-    """HBM bytes per filter launch from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+def measured_traffic(path=None):
+    """HBM bytes per filter launch from a committed counter summary (default:
+    the 100^3 step's), or None when the kernel source has changed since the
+    counters were taken."""
     import hashlib
-    if not os.path.exists(COUNTERS):
+    path = path or COUNTERS
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()

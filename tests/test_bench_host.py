@@ -27,6 +27,7 @@ def test_counter_summary_matches_the_measured_kernel_source():
     src = bench.filter_kernel_source()
     assert "k_cheb_blk_lds" in src and "template void cheb_blk<double>" in src
     assert bench.measured_traffic() is not None
+    assert bench.measured_traffic(bench.COUNTERS_C3) is not None
     assert hashlib.sha256((src + " ").encode()).hexdigest() != \
         hashlib.sha256(src.encode()).hexdigest()
 

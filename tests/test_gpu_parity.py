@@ -694,35 +694,58 @@ def test_lanczos_dos_matches_oracle(ctx, N, dim, pot):
             assert abs(a - b) <= 1e-8 * A.n, (x0, x1, sigma, a, b)
 
 
-def test_headline_workload_sampled_pairs_against_oracle(ctx):
-    """At the headline size and launch configuration (100^3 + potential, KPM
-    cut of [0.60, 0.70] into 10 slices, autotuned groups), the first slice's
-    pairs: every residual <= 1e-8, orthonormal vectors, and eight sampled pairs
-    re-checked with the oracle's FP64 product on the host."""
+def test_headline_workload_slices_equal_the_oracle(ctx):
+    """The 100^3 workload (3-D 7-point Laplacian + U[0,1) potential, KPM cut of
+    [0.60, 0.70] into 10 slices, degree 80 x 20 probes) against the oracle's
+    own run of it (tests/golden/c2_oracle.json, written by
+    tests/golden/make_c2_golden.py from oracle/ alone): the device spectrum
+    bounds, KPM moments and slice ends agree with the oracle's, and slices 0
+    and 9 (the lowest and highest filter degree), solved together in one batch
+    with the autotuned group width, return exactly the oracle's eigenvalue
+    lists (same count, each within 1e-10 relative), residuals <= 1e-8 and
+    orthonormal vectors; sampled pairs are re-checked with the oracle's FP64
+    product on the host."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")))
     A = I.laplacian(100, 3, pot_seed=0)
     Ad = ev.DeviceCsr.from_host(A)
     lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    normA = max(abs(lo), abs(hi))
+    assert abs(lo - gold["bounds"][0]) <= 1e-8 * normA
+    assert abs(hi - gold["bounds"][1]) <= 1e-8 * normA
     intv = [0.60, 0.70, lo, hi]
     mom, est = ev.evsl_kpm_dos(ctx, Ad, intv, 80, 20, seed=1, damping=ev.DAMP_JACKSON)
+    omom = np.array(gold["kpm_moments"])
+    assert np.abs(mom - omom).max() <= 1e-10 * A.n
     sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, intv, 10, 2000)
-    iv = [sli[0], sli[1], lo, hi]
-    cnt = ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, sli[0], sli[1])
-    pol = _pol(iv)
-    g, _ = ev.evsl_autotune(ctx, Ad, 10)
-    lam, Y, res, st = ev.evsl_filtered_lanczos_batch(
-        ctx, Ad, [iv], [pol], [ev.lan_opts(tol=1e-8, seed=2, nev_est=int(cnt * 1.1) + 5)])[0]
+    grid_step = 0.1 / 1999
+    assert np.abs(sli - np.array(gold["slices"])).max() <= grid_step * 1.0001
+    qs = sorted(int(q) for q in gold["solved"])
+    assert qs == [0, 9]
+    ivs = [[gold["solved"][str(q)]["interval"][0], gold["solved"][str(q)]["interval"][1], lo, hi]
+           for q in qs]
+    pols = [_pol(iv) for iv in ivs]
+    assert [p.deg for p in pols] == [gold["solved"][str(q)]["degree"] for q in qs]
+    opts = [ev.lan_opts(tol=1e-8, seed=2 + q, nev_est=gold["solved"][str(q)]["nev_est"])
+            for q in qs]
+    ev.evsl_autotune(ctx, Ad, 10)
+    outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
     ctx.set_group_width(0)
-    assert st["status"] == ev.EVSL_OK and len(lam) >= 0.7 * cnt
-    assert res.max() <= 1e-8
-    Yc = Y.contiguous()
-    G = (Yc.T.contiguous() @ Yc).cpu().numpy()
-    assert np.abs(G - np.eye(len(lam))).max() <= 1e-10
-    normA = max(abs(lo), abs(hi))
-    for j in np.linspace(0, len(lam) - 1, 8).astype(int):
-        y = Y[:, j].cpu().numpy()
-        r = np.linalg.norm(oracle.spmv(A, y) - lam[j] * y) / np.linalg.norm(y) / normA
-        assert r <= 1e-8, (j, r)
-        assert abs(y @ oracle.spmv(A, y) / (y @ y) - lam[j]) <= 1e-12 * normA
+    for q, iv, (lam, Y, res, st) in zip(qs, ivs, outs):
+        want = np.array(gold["solved"][str(q)]["eigenvalues"])
+        keep = (lam >= iv[0]) & ((lam < iv[1]) | (q == 9))
+        assert st["status"] == ev.EVSL_OK
+        assert keep.sum() == len(want), (q, int(keep.sum()), len(want))
+        assert_eigs_match(lam[keep], want, normA)
+        assert res.max() <= 1e-8
+        Yc = Y.contiguous()
+        G = (Yc.T.contiguous() @ Yc).cpu().numpy()
+        assert np.abs(G - np.eye(len(lam))).max() <= 1e-10
+        for j in np.linspace(0, len(lam) - 1, 4).astype(int):
+            y = Y[:, j].cpu().numpy()
+            r = np.linalg.norm(oracle.spmv(A, y) - lam[j] * y) / np.linalg.norm(y) / normA
+            assert r <= 1e-8, (q, j, r)
 
 
 def test_failed_device_allocation_reports_enomem_and_context_survives(ctx):

@@ -42,6 +42,12 @@ extern "C" {
                             (a Ritz value of p(A-hat) exceeds sum |coef_j|, the bound of |p| on
                             [-1, 1], or a non-finite value appears) */
 #define EVSL_ENOTIMPL 7  /* option not implemented */
+#define EVSL_ESCRATCH 8  /* the problem needs more device scratch than the allocation-free
+                            entry point holds (EVSL_NOALLOC_SCRATCH_BYTES) */
+
+/* Bytes of the allocation-free entry point's device scratch: one array per
+ * device, held from the library's load until the process ends. */
+#define EVSL_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 /* ---- value types ---- */
 #define EVSL_F64 0
@@ -251,6 +257,27 @@ int evsl_cheb_coeffs(const double intv[4], int damping, double tau, double tau_e
 int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
                       const int32_t *col_group, const void *V, void *Y, int64_t ldv,
                       int ncols, int prec);
+
+/* ---- allocation-free filter application ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as evsl_filter_apply, with every device
+ * buffer beyond V and Y (the coefficient table, 8 * ncols * (max degree + 1)
+ * bytes, and the two recurrence blocks, 2 * n * ldv values, each rounded up to
+ * 256 bytes) taken from a static device array of EVSL_NOALLOC_SCRATCH_BYTES
+ * per device instead of the context's workspace; it reads the 32-bit column
+ * indices (no 16-bit offset table is built). Calls no hipMalloc, hipFree or
+ * other allocating routine. Returns EVSL_ESCRATCH, with nothing launched,
+ * when the buffers do not fit the array. Every call on a device shares that
+ * device's array, which keeps the last call's contents (the recurrence blocks
+ * are cleared by a kernel at the start of each call): calls that overlap on
+ * one device, on any streams or contexts, race. The array's device address is
+ * looked up in evsl_create (hipGetSymbolAddress), once per device.
+ * Synchronises the context's stream once, after uploading the coefficient
+ * table, as evsl_filter_apply does. */
+int evsl_filter_apply_noalloc(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols,
+                              int npol, const int32_t *col_group, const void *V, void *Y,
+                              int64_t ldv, int ncols, int prec);
 
 /* ---- 5. filtered thick-restart Lanczos with locking (ChebLanTr,
  * Algorithm alg:FiltLanTR) on one slice ----

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libevsl_mi355.so")
 
 EVSL_OK, EVSL_EINVAL, EVSL_ENOMEM, EVSL_EHIP, EVSL_EDEGREE, EVSL_ENOCONV, EVSL_ESPECTRUM, \
-    EVSL_ENOTIMPL = range(8)
+    EVSL_ENOTIMPL, EVSL_ESCRATCH = range(9)
+EVSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 EVSL_F64, EVSL_F32 = 0, 1
 EVSL_LAN_TR, EVSL_LAN_NR = 0, 1
 DAMP_NONE, DAMP_SIGMA, DAMP_JACKSON = 0, 1, 2
@@ -34,6 +35,7 @@ EXPORTS = [
     "evsl_set_graphs", "evsl_lanczos_dos", "evsl_lanczos_count", "evsl_slice_spectrum_lanczos",
     "evsl_lspol", "evsl_spectrum_bounds_gen", "evsl_filtered_lanczos_gen",
     "evsl_set_block_schedule", "evsl_get_block_schedule", "evsl_autotune_schedule",
+    "evsl_filter_apply_noalloc",
 ]
 
 
@@ -102,6 +104,7 @@ def _lib():
         L.evsl_filter_apply.argtypes = [C.c_void_p, C.POINTER(CsrT), C.POINTER(PolT), C.c_int,
                                         C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_int64,
                                         C.c_int, C.c_int]
+        L.evsl_filter_apply_noalloc.argtypes = L.evsl_filter_apply.argtypes
         L.evsl_filtered_lanczos.argtypes = [C.c_void_p, C.POINTER(CsrT), _dp, C.POINTER(PolT),
                                             C.POINTER(LanOptsT), C.POINTER(EigsT)]
         L.evsl_filtered_lanczos_batch.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, _dp,
@@ -427,6 +430,12 @@ def evsl_filter_apply(ctx, A, pols, col_group, V, Y, prec=None):
     _filter_call(_lib().evsl_filter_apply, "evsl_filter_apply", ctx, A, pols, col_group, V, Y,
                  prec)
 
+
+def evsl_filter_apply_noalloc(ctx, A, pols, col_group, V, Y, prec=None):
+    """evsl_filter_apply with its scratch in the library's static device array
+    (no device allocation); EvslError(EVSL_ESCRATCH) when it does not fit."""
+    _filter_call(_lib().evsl_filter_apply_noalloc, "evsl_filter_apply_noalloc", ctx, A, pols,
+                 col_group, V, Y, prec)
 
 
 def lan_opts(m=0, max_its=0, ncycle=0, tol=1e-8, seed=2, nev_est=0, nev_cap=0, prec=EVSL_F64,

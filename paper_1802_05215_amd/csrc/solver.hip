@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <unordered_map>
@@ -23,6 +24,35 @@
 using namespace evc;
 
 namespace {
+
+// Scratch of the allocation-free filter entry point: one array per device,
+// shared by every call on that device (calls that overlap on one device
+// race). Host code uses the device address from hipGetSymbolAddress, taken
+// once per device (scratch_ptr), never the array's name.
+constexpr size_t kScratchBytes = (size_t)EVSL_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device); null when the lookup fails.
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 
 // --------------------------------------------------------------------------
@@ -869,6 +899,7 @@ const char *evsl_strerror(int code) {
     case EVSL_ENOCONV: return "not converged within max_its";
     case EVSL_ESPECTRUM: return "filter blow-up: spectrum bounds do not contain the spectrum";
     case EVSL_ENOTIMPL: return "not implemented";
+    case EVSL_ESCRATCH: return "problem exceeds the allocation-free entry point's scratch";
     default: return "unknown error";
   }
 }
@@ -882,6 +913,11 @@ int evsl_create(evsl_ctx_t *ctx, void *stream, const evsl_alloc_t *alloc) {
   c->stream = (hipStream_t)stream;
   if (alloc) c->alloc = *alloc;
   if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return EVSL_EHIP;
+  }
+  // device address of the allocation-free entry point's scratch on this device
+  if (!scratch_ptr(c->device)) {
     delete c;
     return EVSL_EHIP;
   }
@@ -1402,11 +1438,14 @@ int evsl_slice_spectrum_lanczos(const double *nodes, const double *weights, cons
 
 namespace {
 
-// Y = p(A-hat) V (eq:Cheb0) for a block of columns with per-column filters;
-// the coefficient table and the two recurrence buffers are context workspace.
+// Y = p(A-hat) V (eq:Cheb0) for a block of columns with per-column filters.
+// With scr == nullptr the coefficient table and the two recurrence buffers
+// are context workspace and the 16-bit column offsets are built; otherwise
+// they are carved from scr (scr_bytes long) and the 32-bit indices are read,
+// so nothing is allocated.
 int filter_apply_impl(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
                       const int32_t *col_group, const void *V, void *Y, int64_t ldv, int ncols,
-                      int prec) {
+                      int prec, unsigned char *scr, size_t scr_bytes) {
   if (!ctx || !pols || npol < 1 || !col_group || !V || !Y || ncols < 1 || ldv < ncols ||
       (prec != EVSL_F64 && prec != EVSL_F32))
     return EVSL_EINVAL;
@@ -1446,14 +1485,23 @@ int filter_apply_impl(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
   hipStream_t s = ctx->stream;
   const size_t es = prec == EVSL_F64 ? 8 : 4;
   const size_t tab_bytes = sizeof(double) * tab.size(), blk_bytes = es * (size_t)n * ldv;
-  double *ctab = (double *)ws(ctx, 10, tab_bytes);
-  void *Wa = ws(ctx, 11, blk_bytes);
-  void *Wb = ws(ctx, 12, blk_bytes);
+  double *ctab;
+  void *Wa, *Wb;
+  if (scr) {
+    if (align256(tab_bytes) + 2 * align256(blk_bytes) > scr_bytes) return EVSL_ESCRATCH;
+    ctab = (double *)scr;
+    Wa = scr + align256(tab_bytes);
+    Wb = scr + align256(tab_bytes) + align256(blk_bytes);
+  } else {
+    ctab = (double *)ws(ctx, 10, tab_bytes);
+    Wa = ws(ctx, 11, blk_bytes);
+    Wb = ws(ctx, 12, blk_bytes);
+  }
   HC(ctx, hipMemcpyAsync(ctab, tab.data(), tab_bytes, hipMemcpyHostToDevice, s));
   // the table lives on this frame: wait for the upload before returning
   HC(ctx, hipStreamSynchronize(s));
   evk::Csr Ac = to_csr(A);
-  attach_col_offsets(ctx, A, Ac);
+  if (!scr) attach_col_offsets(ctx, A, Ac);
   // the timer's events and bookkeeping are host-side; none allocates device memory
   FilterTimer tm(ctx);
   double bytes = 0.0;
@@ -1516,7 +1564,17 @@ int filter_apply_impl(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pol
 int evsl_filter_apply(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols, int npol,
                       const int32_t *col_group, const void *V, void *Y, int64_t ldv, int ncols,
                       int prec) {
-  return filter_apply_impl(ctx, A, pols, npol, col_group, V, Y, ldv, ncols, prec);
+  return filter_apply_impl(ctx, A, pols, npol, col_group, V, Y, ldv, ncols, prec, nullptr, 0);
+}
+
+int evsl_filter_apply_noalloc(evsl_ctx_t ctx, const evsl_csr_t *A, const evsl_pol_t *pols,
+                              int npol, const int32_t *col_group, const void *V, void *Y,
+                              int64_t ldv, int ncols, int prec) {
+  if (!ctx) return EVSL_EINVAL;
+  void *p = scratch_ptr(ctx->device);
+  if (!p) return EVSL_EHIP;
+  return filter_apply_impl(ctx, A, pols, npol, col_group, V, Y, ldv, ncols, prec,
+                           (unsigned char *)p, kScratchBytes);
 }
 
 int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv[4],

@@ -52,6 +52,9 @@ def parse():
                     help="skip the 200^3 x 512-column filter leg of the default run")
     ap.add_argument("--c3-only", action="store_true",
                     help="only the 200^3 x 512-column filter leg (its own JSON line)")
+    ap.add_argument("--c3-kpm-degree", type=int, default=2000,
+                    help="200^3 leg: KPM degree of the cut (degree 80 cannot resolve the "
+                         "spectrum's lower edge)")
     ap.add_argument("--c3-degree", type=int, default=24,
                     help="200^3 leg: degree of the truncated filters (launches per application "
                          "= degree + 1)")
@@ -306,7 +309,7 @@ def cpu_baseline(A, rec, args, c3=None, budget_s=25.0):
 def c3_filter_leg(ctx, ev, args, log):
     """The batched 200^3 workload's filter step: 3-D 7-point Laplacian 200^3 +
     U[0,1) potential (seed 0), interval [lambda_min, eta] with eta where the
-    KPM count (degree 80, 20 probes) reaches 512, cut into 32 KPM slices; the
+    KPM count (degree 2000, 20 probes) reaches 512, cut into 32 KPM slices; the
     512-column block (16 columns per slice, Gaussian, torch generator seed 0)
     filtered by one Clenshaw degree step per launch over all 512 columns
     (FP64). Every slice's filter is truncated to the same degree so that each
@@ -323,7 +326,7 @@ def c3_filter_leg(ctx, ev, args, log):
     A = I.laplacian(N, 3, pot_seed=0)
     Ad = ev.DeviceCsr.from_host(A, device="cuda:0")
     lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
-    mom, _ = ev.evsl_kpm_dos(ctx, Ad, [lo, hi, lo, hi], 80, 20, seed=1,
+    mom, _ = ev.evsl_kpm_dos(ctx, Ad, [lo, hi, lo, hi], args.c3_kpm_degree, 20, seed=1,
                              damping=ev.DAMP_JACKSON)
     cnt = lambda x0, x1: ev.evsl_kpm_count(mom, ev.DAMP_JACKSON, lo, hi, x0, x1)
     a, b = lo, hi
@@ -359,7 +362,8 @@ def c3_filter_leg(ctx, ev, args, log):
     step_bytes = m_a + 4.0 * A.n * ncols * 8
     out = {
         "workload": (f"batched filter: 3-D 7-point Laplacian {N}^3 + U[0,1) potential (seed 0), "
-                     f"[lambda_min, eta_512] = [{lo:.6g}, {eta:.6g}] cut into {nsl} KPM slices, "
+                     f"[lambda_min, eta_512] = [{lo:.6g}, {eta:.6g}] cut into {nsl} KPM slices "
+                     f"(degree {args.c3_kpm_degree}), "
                      f"{ncols} columns ({ncols // nsl} per slice), FP64 Clenshaw degree step "
                      f"over all {ncols} columns per launch"),
         "n": A.n, "nnz": A.nnz, "columns": ncols,

@@ -3,9 +3,11 @@
 
 Workload: 3-D 7-point Laplacian on a 200^3 grid (h = 1, Dirichlet) plus the
 diagonal potential U[0,1) of seed 0; interval [lambda_min, eta] with lambda_min
-the Lanczos lower bound and eta where the KPM count (degree 80, 20 Rademacher
-probes of seed 1, Jackson damping) from lambda_min reaches 512 (60 bisection
-halvings); that interval cut into 32 slices on a 2000-point grid; Jackson
+the Lanczos lower bound and eta where the KPM count (degree 2000, 20
+Rademacher probes of seed 1, Jackson damping) from lambda_min reaches 512 (60
+bisection halvings); that interval cut into 32 slices on a 2000-point grid (a
+degree-80 estimate cannot resolve the spectrum's lower edge: it places 512
+eigenvalues below 0.4953, where degrees 1000-4000 agree on about 201); Jackson
 filters with tau = 0.8 (boundary slices tau_ext = 0.4); thick-restart filtered
 Lanczos (Algorithm alg:FiltLanTR) at tolerance 1e-8 with the start vector of
 stream 2 + slice index and nev_est = 1.1 x the slice's KPM count + 5.
@@ -34,7 +36,7 @@ from tests.golden.make_c2_golden import cpu_model, log  # noqa: E402
 OUT = os.path.join(HERE, "c3_oracle.json")
 JACKSON = 2
 NSLICES, TARGET = 32, 512
-KPM_DEGREE, KPM_VECTORS = 80, 20
+KPM_DEGREE, KPM_VECTORS = 2000, 20
 TOL = 1e-8
 
 
@@ -60,7 +62,7 @@ def main(slices):
     prev = json.load(open(OUT)) if os.path.exists(OUT) else {}
     rec = {
         "workload": ("3-D 7-point Laplacian 200^3 + U[0,1) potential (seed 0), [lambda_min, "
-                     "eta_512] by the KPM count (degree 80 x 20 Rademacher probes, seed 1, "
+                     "eta_512] by the KPM count (degree 2000 x 20 Rademacher probes, seed 1, "
                      "Jackson), 32 slices, Jackson filters tau 0.8, thick-restart filtered "
                      "Lanczos, tol 1e-8"),
         "script": "tests/golden/make_c3_golden.py",

@@ -99,7 +99,7 @@ typedef struct {
   int m;          /* Krylov dimension per cycle; 0: max(3 nev_est + 30, 60);
                      EVSL_LAN_NR: total step cap; 0: max(5 nev_est + 200, 400) */
   int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) (EVSL_LAN_NR: m) */
-  int ncycle;     /* early-restart test period; 0: 30 */
+  int ncycle;     /* early-restart test period; 0: 10 (EVSL_LAN_TR), 30 (EVSL_LAN_NR) */
   double tol;     /* residual tolerance ||A u - lambda u|| / ||A||; 0: 1e-8 */
   uint64_t seed;  /* start-vector stream (SplitMix64); restarts draw further blocks */
   int nev_est;    /* expected count in the slice (sizing only); 0: 50 */
@@ -429,14 +429,20 @@ int evsl_set_block_variant(int variant);
  *          all rows; within a chunk, row blocks are dealt to the XCDs in runs
  *          of `group` consecutive blocks, so all XCDs sweep the same rows
  *          together while each keeps short runs of neighbouring rows.
- * A chunk as wide as the block, or not a multiple of the lane width, falls
- * back to map 1; so do the KPM steps. */
-int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group);
-int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group);
+ * lane_cols: block columns per lane (0: 16-byte lanes, i.e. 2 FP64 or 4 FP32;
+ * 1, 2 or 4 when the block's width, leading dimension and alignment allow,
+ * else halved until they do). A chunk as wide as the block, or not a multiple
+ * of the lane width, falls back to map 1; so do the KPM steps. EVSL_EINVAL
+ * for a map outside 0-2, a map-2 chunk or group below 1, or another lane
+ * width. */
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols);
+int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group,
+                            int *lane_cols);
 /* Times the Clenshaw degree step of the block filter (eq:Cheb0 evaluated by
  * Clenshaw's recurrence) on A over an n x ncols block of scratch vectors for
  * each candidate schedule (maps 0 and 1; map 2 with chunks of 16-128 columns
- * and runs of 1-64 row blocks), keeps the fastest in the context and
+ * and runs of 1-64 row blocks; in FP64 each also with 4 columns per lane),
+ * keeps the fastest in the context and
  * returns its milliseconds per step. Uses 3 n x ncols blocks of workspace
  * (value size by prec). Synchronous. */
 int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int prec,

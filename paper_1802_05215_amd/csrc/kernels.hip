@@ -40,6 +40,9 @@ __device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2). Remapping gives XCD x a contiguous range of logical blocks, so rows
 // that are neighbours in the matrix (and read each other's vector entries)
@@ -464,19 +467,34 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk_lds(int n, int nc, int rows_pe
             g[u] = *(const vt *)(wc + roff(c));
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc += a[u] * g[u];
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fma_t(a[u], g[u][v], acc[v]);
         }
       } else {
-        for (int k = kb + nz0; k < ke + nz0; ++k)
-          acc += va[k] * *(const vt *)(wc + roff(DELTA ? row + (int)cd[k] : ci[k]));
+        for (int k = kb + nz0; k < ke + nz0; ++k) {
+          const vt g = *(const vt *)(wc + roff(DELTA ? row + (int)cd[k] : ci[k]));
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = fma_t(va[k], g[v], acc[v]);
+        }
       }
-      vt wn = s1 * acc + s0 * w;
-      if (HAS_PREV) wn -= wp;
-      if (IS_CLEN) wn += c1 * vd;
+      // element by element with explicit fused multiply-adds, so that every
+      // lane width (and so every schedule) rounds the same way
+      vt wn;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        T x = fma_t(s1, acc[v], s0 * w[v]);
+        if (HAS_PREV) x = x - wp[v];
+        if (IS_CLEN) x = fma_t(c1[v], vd[v], x);
+        wn[v] = x;
+      }
       *(vt *)(Wn + e) = wn;
       if (HAS_Y) {
-        const vt y = Y_INIT ? c0 * w : yo;
-        *(vt *)(Y + e) = y + c1 * wn;
+        vt y;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          y[v] = fma_t(c1[v], wn[v], Y_INIT ? c0[v] * w[v] : yo[v]);
+        *(vt *)(Y + e) = y;
       }
       if (HAS_DOT) {
 #pragma unroll
@@ -497,9 +515,10 @@ static int g_blk_variant = 2;
 void set_blk_variant(int v) { g_blk_variant = (v >= 1 && v <= 4) ? v : 2; }
 
 // Columns per lane for a launch: 2 (16-byte loads) when the block allows it.
-static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int np) {
+static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int np, int want) {
   if (g_blk_variant != 2) return 1;
   int v = es == 8 ? 2 : 4;  // 16-byte loads
+  if (want == 4 || want == 2 || want == 1) v = want;  // the schedule's lane width
   while (v > 1) {
     bool ok = (nc % v == 0) && (ld % v == 0);
     for (int i = 0; ok && i < np; ++i)
@@ -562,9 +581,9 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
                     (int64_t)nc * cld < ((int64_t)1 << 31);
   const int var = ok32 ? g_blk_variant : 1;
   const void *ptrs[5] = {W, Wp, Wn, Y, Vd};
-  const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5);
+  const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5, sched ? sched->vec : 0);
   // the global-load kernel (variant 1) takes no schedule: one chunk
-  const BlkSched sc = var == 1 ? BlkSched{0, nc, 1} : blk_resolve(sched, nc, vec, kind);
+  const BlkSched sc = var == 1 ? BlkSched{0, nc, 1, 0} : blk_resolve(sched, nc, vec, kind);
   int rpw;
   dim3 grid;
   blk_shape(A.n, sc.cw, vec, &rpw, &grid);

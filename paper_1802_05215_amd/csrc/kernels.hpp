@@ -48,11 +48,13 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
 
 // Launch schedule of the block filter (see k_cheb_blk_lds): map 0 launch
 // order, 1 contiguous row ranges per XCD, 2 column chunks of cw columns one
-// after another with row blocks dealt to the XCDs in runs of grp.
+// after another with row blocks dealt to the XCDs in runs of grp; vec: columns
+// per lane (0: 16-byte lanes; 1, 2 or 4 when the block's alignment allows).
 struct BlkSched {
   int map = 1;
   int cw = 0;
   int grp = 1;
+  int vec = 0;
 };
 
 // Row-major block n x ld, first nc columns active. For the KPM kinds, Vd is
@@ -64,7 +66,8 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
               const T *Wp, T *Wn, T *Y, int64_t ld, int nc, const double *coef, int cld, int jnext,
               const T *Vd, double *partial, const BlkSched *sched = nullptr);
 int blk_partials(int n, int nc);
-// Block kernel choice: 1 global loads, 2 LDS-staged + XCD remap (default), 3 LDS-staged.
+// Block kernel choice: 1 global loads, 2 LDS-staged and scheduled (default), 3 LDS-staged,
+// one column per lane, launch order, 4 as 2 with one column per lane.
 void set_blk_variant(int v);
 
 // Gather / scatter FP64 columns into / out of a row-major block of type TB:

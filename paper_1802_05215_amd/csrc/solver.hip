@@ -237,7 +237,10 @@ struct Slice {
     if (m < 2) fail(EVSL_EINVAL);
     max_its = nr ? m : (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
     cmax = nr ? std::min(m, m_tr) : m;
-    ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : 30;
+    // early-restart test period: every 10 steps for thick restart (each restart
+    // cycle, including the final no-candidate ones, lasts at least two tests),
+    // every 30 for the non-restart form, whose settle test ends the whole run
+    ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : (nr ? 30 : 10);
     tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
     seed = opt ? opt->seed : 0;
     nev_cap = (opt && opt->nev_cap > 0) ? opt->nev_cap : std::max(2 * nev_est + 40, 100);
@@ -975,19 +978,24 @@ int evsl_set_block_variant(int variant) {
   return EVSL_OK;
 }
 
-int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group) {
-  if (!ctx || map < 0 || map > 2 || (map == 2 && (chunk_cols < 1 || group < 1))) return EVSL_EINVAL;
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols) {
+  if (!ctx || map < 0 || map > 2 || (map == 2 && (chunk_cols < 1 || group < 1)) ||
+      (lane_cols != 0 && lane_cols != 1 && lane_cols != 2 && lane_cols != 4))
+    return EVSL_EINVAL;
   ctx->blk_sched.map = map;
   ctx->blk_sched.cw = map == 2 ? chunk_cols : 0;
   ctx->blk_sched.grp = map == 2 ? group : 1;
+  ctx->blk_sched.vec = lane_cols;
   return EVSL_OK;
 }
 
-int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group) {
+int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group,
+                            int *lane_cols) {
   if (!ctx) return EVSL_EINVAL;
   if (map) *map = ctx->blk_sched.map;
   if (chunk_cols) *chunk_cols = ctx->blk_sched.cw;
   if (group) *group = ctx->blk_sched.grp;
+  if (lane_cols) *lane_cols = ctx->blk_sched.vec;
   return EVSL_OK;
 }
 
@@ -1026,10 +1034,14 @@ int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int p
   // candidates: one chunk (XCD row ranges, launch order), then column chunks
   // of 16..128 columns with row blocks dealt to the XCDs in runs of 1..64
   std::vector<evk::BlkSched> cand;
-  cand.push_back({1, 0, 1});
-  cand.push_back({0, 0, 1});
-  for (int cw = 16; cw <= 128 && cw < ncols; cw *= 2)
-    for (int grp : {1, 4, 16, 64}) cand.push_back({2, cw, grp});
+  const int lanes[2] = {0, 4};
+  for (int li = 0; li < (prec == EVSL_F64 ? 2 : 1); ++li) {
+    const int vec = lanes[li];
+    cand.push_back({1, 0, 1, vec});
+    cand.push_back({0, 0, 1, vec});
+    for (int cw = 16; cw <= 128 && cw < ncols; cw *= 2)
+      for (int grp : {1, 4, 16, 64}) cand.push_back({2, cw, grp, vec});
+  }
   hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
   const int reps = 4;
   const double sc = 1e-3;  // contractive: the scratch values stay bounded

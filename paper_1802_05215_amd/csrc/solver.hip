@@ -136,6 +136,8 @@ struct Slice {
   // lock_off; candidates are checked in chunks of cmax columns
   bool nr = false;
   int lock_off = 0, cmax = 0;
+  // shortest thick-restart cycle that a settled early-restart test may end
+  static constexpr int kMinCycle = 30;
   double tol_lo = 0.0;
   // polish_max < 0: no FP64 phase; npolish: 1 once the FP64 phase has started
   int polish_max = 0, npolish = 0, nguard = 0, nstall = 0;
@@ -237,9 +239,9 @@ struct Slice {
     if (m < 2) fail(EVSL_EINVAL);
     max_its = nr ? m : (opt && opt->max_its > 0) ? opt->max_its : std::max(20 * m, 2000);
     cmax = nr ? std::min(m, m_tr) : m;
-    // early-restart test period: every 10 steps for thick restart (each restart
-    // cycle, including the final no-candidate ones, lasts at least two tests),
-    // every 30 for the non-restart form, whose settle test ends the whole run
+    // early-restart test period: every 10 steps for thick restart (a cycle still
+    // lasts at least kMinCycle steps), every 30 for the non-restart form, whose
+    // settle test ends the whole run
     ncycle = (opt && opt->ncycle > 0) ? opt->ncycle : (nr ? 30 : 10);
     tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
     seed = opt ? opt->seed : 0;
@@ -527,7 +529,11 @@ struct Slice {
       t_new = 0.0;
       for (double x : w)
         if (x >= bar) t_new += x;
-      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new)))
+      // a settled sum ends the cycle once it has run at least kMinCycle steps:
+      // a cycle after a restart that found nothing (a fresh random vector) must
+      // grow long enough to show an eigenvalue the filter separates weakly
+      if (std::fabs(t_new - t_old) < 1e-10 * std::max(1.0, std::fabs(t_new)) &&
+          (nr || (i + 1) - l >= kMinCycle))
         end_cycle = settled = true;
     }
     if (its > max_its) end_cycle = true;

@@ -203,6 +203,11 @@ def one_step(ctx, ev, Ad, args):
     else:
         ctx.set_group_width(args.group_width)
         gw, us = args.group_width, None
+    sched = None
+    if Ad.n >= 4_000_000 and min(gw or len(sel), len(sel)) >= 4:
+        # large matrices: the block filter's launch schedule for the group width
+        sched = ev.evsl_autotune_schedule(ctx, Ad, min(gw or len(sel), len(sel)),
+                                          ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64)
     t_setup = time.perf_counter() - t0
     if args.method == "si":
         if args.mode == "batch":
@@ -234,7 +239,8 @@ def one_step(ctx, ev, Ad, args):
                               t_orth=st["t_orth"], t_ritz=st["t_ritz"], status=st["status"],
                               npolish=st["npolish"]))
     lam_all = np.concatenate(lams)
-    return dict(t=t_tot, t_setup=t_setup, group_width=gw, tune_us=us, nev=len(lam_all), lam=lam_all,
+    return dict(t=t_tot, t_setup=t_setup, group_width=gw, tune_us=us, schedule=sched,
+                nev=len(lam_all), lam=lam_all,
                 res=np.concatenate(ress), bounds=(lo, hi), kpm_est=est, slices=sli, interval=intv[:2],
                 per_slice=per_slice, pols=pols, ivs=ivs)
 
@@ -372,7 +378,8 @@ def c3_filter_leg(ctx, ev, args, log):
         "slice_degrees": [p.deg for p in real],
         "timed_degree": kstep, "launches": fs["launches"],
         "schedule": {"map": sched[0], "chunk_cols": sched[1], "group": sched[2],
-                     "lane_cols": sched[3], "tuner_ms_per_step": sched[4]},
+                     "lane_cols": sched[3], "rows_per_wg": sched[4], "lds_staging": sched[5],
+                     "tuner_ms_per_step": sched[6]},
         "ms_per_launch": fs["seconds"] / fs["launches"] * 1e3,
         "bytes_per_step": step_bytes,
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -382,7 +389,7 @@ def c3_filter_leg(ctx, ev, args, log):
         "setup_s": t_setup,
     }
     tb = measured_traffic(COUNTERS_C3)
-    if tb is not None and sched[:4] == (2, 64, 64, 0):
+    if tb is not None and sched[:6] == (2, 64, 64, 0, 0, 1):
         # the counters were taken with this schedule
         out["roofline"]["traffic"] = tb / (fs["seconds"] / fs["launches"]) / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = tb
@@ -396,7 +403,7 @@ def c3_filter_leg(ctx, ev, args, log):
                                "cc": p.cc, "dd": p.dd, "coef": p.coef}
         out["A_host"] = A
     del V, Y
-    ctx.set_block_schedule(1, 0, 1, 0)
+    ctx.set_block_schedule(1, 0, 1, 0, 0, 1)
     torch.cuda.empty_cache()
     return out
 
@@ -1144,6 +1151,7 @@ def main():
             "filter_degrees": [s["deg"] for s in rec["per_slice"]],
             "max_its": args.max_its,
             "group_width": rec["group_width"],
+            "block_schedule": rec["schedule"],
         },
         "setup_s": rec["t_setup"],
         "filter_gbps": achieved,

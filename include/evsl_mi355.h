@@ -431,18 +431,24 @@ int evsl_set_block_variant(int variant);
  *          together while each keeps short runs of neighbouring rows.
  * lane_cols: block columns per lane (0: 16-byte lanes, i.e. 2 FP64 or 4 FP32;
  * 1, 2 or 4 when the block's width, leading dimension and alignment allow,
- * else halved until they do). A chunk as wide as the block, or not a multiple
- * of the lane width, falls back to map 1; so do the KPM steps. EVSL_EINVAL
- * for a map outside 0-2, a map-2 chunk or group below 1, or another lane
- * width. */
-int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols);
+ * else halved until they do). rows_per_wg: rows per workgroup (0: four passes
+ * of the workgroup's row group; else rounded down to whole passes, at most 256).
+ * lds_staging 0: the kernel that reads the CSR rows from global memory without
+ * staging them in LDS (one chunk, launch order, one column per lane; 1: the
+ * LDS-staged kernel). A chunk as wide as the block, or not a multiple of the
+ * lane width, falls back to map 1; so do the KPM steps. EVSL_EINVAL for a map
+ * outside 0-2, a map-2 chunk or group below 1, another lane width, rows_per_wg
+ * outside 0-256 or lds_staging other than 0 or 1. */
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols,
+                            int rows_per_wg, int lds_staging);
 int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group,
-                            int *lane_cols);
+                            int *lane_cols, int *rows_per_wg, int *lds_staging);
 /* Times the Clenshaw degree step of the block filter (eq:Cheb0 evaluated by
  * Clenshaw's recurrence) on A over an n x ncols block of scratch vectors for
  * each candidate schedule (maps 0 and 1; map 2 with chunks of 16-128 columns
- * and runs of 1-64 row blocks; in FP64 each also with 4 columns per lane),
- * keeps the fastest in the context and
+ * and runs of 1-64 row blocks; in FP64 each also with 4 columns per lane), then
+ * for the fastest one 1, 2 and 8 passes per workgroup and the kernel without
+ * LDS staging, keeps the fastest in the context and
  * returns its milliseconds per step. Uses 3 n x ncols blocks of workspace
  * (value size by prec). Synchronous. */
 int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int prec,

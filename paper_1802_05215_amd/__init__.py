@@ -137,8 +137,8 @@ def _lib():
         L.evsl_autotune.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int,
                                     C.POINTER(C.c_int), _dp]
         L.evsl_set_group_width.argtypes = [C.c_void_p, C.c_int]
-        L.evsl_set_block_schedule.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]
-        L.evsl_get_block_schedule.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip]
+        L.evsl_set_block_schedule.argtypes = [C.c_void_p] + [C.c_int] * 6
+        L.evsl_get_block_schedule.argtypes = [C.c_void_p] + [_ip] * 6
         L.evsl_autotune_schedule.argtypes = [C.c_void_p, C.POINTER(CsrT), C.c_int, C.c_int, _dp]
         L.evsl_copy_probe.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
         L.evsl_filtered_subspace.argtypes = [C.c_void_p, C.POINTER(CsrT), _dp, C.POINTER(PolT),
@@ -244,17 +244,19 @@ class Ctx:
     def set_group_width(self, g):
         _chk(_lib().evsl_set_group_width(self.h, int(g)), "set_group_width")
 
-    def set_block_schedule(self, map, chunk_cols=0, group=1, lane_cols=0):
+    def set_block_schedule(self, map, chunk_cols=0, group=1, lane_cols=0, rows_per_wg=0,
+                           lds_staging=1):
         _chk(_lib().evsl_set_block_schedule(self.h, int(map), int(chunk_cols), int(group),
-                                            int(lane_cols)), "evsl_set_block_schedule")
+                                            int(lane_cols), int(rows_per_wg), int(lds_staging)),
+             "evsl_set_block_schedule")
 
     def block_schedule(self):
-        """(map, chunk columns, row-block run, columns per lane) of the block
-        filter schedule."""
-        m, c, g, v = C.c_int(), C.c_int(), C.c_int(), C.c_int()
-        _chk(_lib().evsl_get_block_schedule(self.h, C.byref(m), C.byref(c), C.byref(g),
-                                            C.byref(v)), "evsl_get_block_schedule")
-        return m.value, c.value, g.value, v.value
+        """(map, chunk columns, row-block run, columns per lane, rows per
+        workgroup, LDS staging) of the block filter schedule."""
+        v = [C.c_int() for _ in range(6)]
+        _chk(_lib().evsl_get_block_schedule(self.h, *[C.byref(x) for x in v]),
+             "evsl_get_block_schedule")
+        return tuple(x.value for x in v)
 
     def mem_stats(self, reset_peak=False):
         """(bytes held now, peak bytes) of the context's device allocations."""
@@ -282,8 +284,7 @@ def evsl_autotune(ctx, A, max_cols, prec=EVSL_F64):
 
 def evsl_autotune_schedule(ctx, A, ncols, prec=EVSL_F64):
     """Picks the block filter schedule for ncols columns on A (kept in ctx);
-    returns (map, chunk columns, row-block run, columns per lane, ms per degree
-    step)."""
+    returns ctx.block_schedule() followed by the ms per degree step."""
     ms = C.c_double()
     _chk(_lib().evsl_autotune_schedule(ctx.h, C.byref(A.t), int(ncols), int(prec), C.byref(ms)),
          "evsl_autotune_schedule")

@@ -321,17 +321,15 @@ __global__ __launch_bounds__(TPB) void k_cheb_blk(int n, int nc, int rows_per_wg
     for (int r = rbeg + rsub; r < rend; r += R0) {
       T acc = 0;
       const int kb = rp[r], ke = rp[r + 1];
-      for (int k = kb; k < ke; ++k) acc += va[k] * W[(int64_t)ci[k] * ld + col];
+      for (int k = kb; k < ke; ++k) acc = fma_t(va[k], W[(int64_t)ci[k] * ld + col], acc);
       const int64_t e = (int64_t)r * ld + col;
       const T w = W[e];
-      T wn = s1 * acc + s0 * w;
-      if (HAS_PREV) wn -= Wp[e];
-      if (IS_CLEN) wn += c1 * Vd[e];
+      // the same fused multiply-adds, in the same order, as the LDS-staged kernel
+      T wn = fma_t(s1, acc, s0 * w);
+      if (HAS_PREV) wn = wn - Wp[e];
+      if (IS_CLEN) wn = fma_t(c1, Vd[e], wn);
       Wn[e] = wn;
-      if (HAS_Y) {
-        const T y = Y_INIT ? c0 * w : Y[e];
-        Y[e] = y + c1 * wn;
-      }
+      if (HAS_Y) Y[e] = fma_t(c1, wn, Y_INIT ? c0 * w : Y[e]);
       if (HAS_DOT) dacc += (double)Vd[e] * (double)wn;
     }
   }
@@ -530,11 +528,15 @@ static int blk_vec(int nc, int64_t ld, size_t es, const void *const *ptrs, int n
 }
 
 // Rows per workgroup and grid for nc columns (one chunk of cw = nc columns).
-static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid) {
+// lds: the LDS-staged kernel, whose row-pointer stage holds at most TPB rows;
+// rows > 0 asks for that many rows per workgroup (rounded to whole passes).
+static void blk_shape(int n, int nc, int vec, int *rows_per_wg, dim3 *grid, bool lds = true,
+                      int rows = 0) {
   const int ncv = nc / vec;
   const int R0 = ncv <= TPB ? TPB / ncv : 1;
   int passes = (ncv <= TPB && R0 > 2) ? 4 : 8;
-  if (g_blk_variant != 1) passes = std::max(1, std::min(passes, TPB / R0));
+  if (rows > 0) passes = std::max(1, rows / R0);
+  if (lds) passes = std::max(1, std::min(passes, TPB / R0));
   *rows_per_wg = R0 * passes;
   const int gx = (n + *rows_per_wg - 1) / *rows_per_wg;
   const int gy = ncv <= TPB ? 1 : (ncv + TPB - 1) / TPB;
@@ -545,7 +547,7 @@ int blk_partials(int n, int nc) {
   // an upper bound over the launch shapes (VEC 1 has the most workgroups)
   int rpw;
   dim3 g;
-  blk_shape(n, nc, 1, &rpw, &g);
+  blk_shape(n, nc, 1, &rpw, &g, g_blk_variant != 1);
   return (int)(g.x * g.y);
 }
 
@@ -559,6 +561,7 @@ static BlkSched blk_resolve(const BlkSched *sc, int nc, int vec, int kind) {
   r.cw = nc;
   r.grp = 1;
   if (!sc || g_blk_variant == 3 || kind == STEP_KPM_FIRST || kind == STEP_KPM_NEXT) return r;
+  r.rows = sc->rows;
   if (sc->map == 0 || sc->map == 1) {
     r.map = sc->map;
     return r;
@@ -579,14 +582,16 @@ void cheb_blk(hipStream_t s, const Csr &A, int kind, double s1, double s0, const
   const bool wide = (int64_t)A.n * ld >= ((int64_t)1 << 31);
   const bool ok32 = ld < ((int64_t)1 << 31) && (int64_t)A.n < ((int64_t)1 << 31) &&
                     (int64_t)nc * cld < ((int64_t)1 << 31);
-  const int var = ok32 ? g_blk_variant : 1;
+  const bool kpm = kind == STEP_KPM_FIRST || kind == STEP_KPM_NEXT;
+  int var = ok32 ? g_blk_variant : 1;
+  if (var != 1 && sched && sched->lds == 0 && !kpm) var = 1;  // the schedule's kernel choice
   const void *ptrs[5] = {W, Wp, Wn, Y, Vd};
   const int vec = var == 1 ? 1 : blk_vec(nc, ld, sizeof(T), ptrs, 5, sched ? sched->vec : 0);
   // the global-load kernel (variant 1) takes no schedule: one chunk
-  const BlkSched sc = var == 1 ? BlkSched{0, nc, 1, 0} : blk_resolve(sched, nc, vec, kind);
+  const BlkSched sc = var == 1 ? BlkSched{0, nc, 1, 0, 0, 0} : blk_resolve(sched, nc, vec, kind);
   int rpw;
   dim3 grid;
-  blk_shape(A.n, sc.cw, vec, &rpw, &grid);
+  blk_shape(A.n, sc.cw, vec, &rpw, &grid, var != 1, sc.rows);
   const int nrb = (int)grid.x;
   int npad = nrb;
   if (sc.map == 2) {

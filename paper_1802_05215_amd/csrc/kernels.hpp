@@ -49,12 +49,17 @@ void cheb_vec(hipStream_t s, const Csr &A, int variant, int kind, double s1, dou
 // Launch schedule of the block filter (see k_cheb_blk_lds): map 0 launch
 // order, 1 contiguous row ranges per XCD, 2 column chunks of cw columns one
 // after another with row blocks dealt to the XCDs in runs of grp; vec: columns
-// per lane (0: 16-byte lanes; 1, 2 or 4 when the block's alignment allows).
+// per lane (0: 16-byte lanes; 1, 2 or 4 when the block's alignment allows);
+// rows: rows per workgroup (0: the default, four passes of the workgroup's
+// row group; else rounded to whole passes, at most 256 rows); lds = 0: the
+// global-load kernel (no LDS staging of the CSR rows, launch order).
 struct BlkSched {
   int map = 1;
   int cw = 0;
   int grp = 1;
   int vec = 0;
+  int rows = 0;
+  int lds = 1;
 };
 
 // Row-major block n x ld, first nc columns active. For the KPM kinds, Vd is

@@ -984,24 +984,30 @@ int evsl_set_block_variant(int variant) {
   return EVSL_OK;
 }
 
-int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols) {
+int evsl_set_block_schedule(evsl_ctx_t ctx, int map, int chunk_cols, int group, int lane_cols,
+                            int rows_per_wg, int lds_staging) {
   if (!ctx || map < 0 || map > 2 || (map == 2 && (chunk_cols < 1 || group < 1)) ||
-      (lane_cols != 0 && lane_cols != 1 && lane_cols != 2 && lane_cols != 4))
+      (lane_cols != 0 && lane_cols != 1 && lane_cols != 2 && lane_cols != 4) ||
+      rows_per_wg < 0 || rows_per_wg > 256 || (lds_staging != 0 && lds_staging != 1))
     return EVSL_EINVAL;
   ctx->blk_sched.map = map;
   ctx->blk_sched.cw = map == 2 ? chunk_cols : 0;
   ctx->blk_sched.grp = map == 2 ? group : 1;
   ctx->blk_sched.vec = lane_cols;
+  ctx->blk_sched.rows = rows_per_wg;
+  ctx->blk_sched.lds = lds_staging;
   return EVSL_OK;
 }
 
 int evsl_get_block_schedule(evsl_ctx_t ctx, int *map, int *chunk_cols, int *group,
-                            int *lane_cols) {
+                            int *lane_cols, int *rows_per_wg, int *lds_staging) {
   if (!ctx) return EVSL_EINVAL;
   if (map) *map = ctx->blk_sched.map;
   if (chunk_cols) *chunk_cols = ctx->blk_sched.cw;
   if (group) *group = ctx->blk_sched.grp;
   if (lane_cols) *lane_cols = ctx->blk_sched.vec;
+  if (rows_per_wg) *rows_per_wg = ctx->blk_sched.rows;
+  if (lds_staging) *lds_staging = ctx->blk_sched.lds;
   return EVSL_OK;
 }
 
@@ -1053,7 +1059,7 @@ int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int p
   const double sc = 1e-3;  // contractive: the scratch values stay bounded
   double best = 1e300;
   evk::BlkSched pick = cand[0];
-  for (const evk::BlkSched &c : cand) {
+  auto time_one = [&](const evk::BlkSched &c) -> double {
     for (int r = -1; r < reps; ++r) {
       if (r == 0) HC(ctx, hipEventRecord(e0, s));
       if (prec == EVSL_F32)
@@ -1069,11 +1075,32 @@ int evsl_autotune_schedule(evsl_ctx_t ctx, const evsl_csr_t *A, int ncols, int p
     HC(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     HC(ctx, hipEventElapsedTime(&ms, e0, e1));
-    const double t = ms / reps;
+    return ms / reps;
+  };
+  auto consider = [&](const evk::BlkSched &c) {
+    const double t = time_one(c);
     if (t < best * 0.99) {  // keep the earlier (simpler) schedule unless clearly faster
       best = t;
       pick = c;
     }
+  };
+  for (const evk::BlkSched &c : cand) consider(c);
+  // second stage on the chosen walk: rows per workgroup (whole passes of the
+  // workgroup's row group), then the global-load kernel without LDS staging
+  {
+    const evk::BlkSched base = pick;
+    const int v = base.vec ? base.vec : (prec == EVSL_F64 ? 2 : 4);
+    const int cw = base.map == 2 ? base.cw : ncols;
+    const int r0 = cw / v <= 256 ? 256 / (cw / v) : 1;
+    for (int passes : {1, 2, 8}) {
+      if (r0 * passes > 256) continue;
+      evk::BlkSched c = base;
+      c.rows = r0 * passes;
+      consider(c);
+    }
+    evk::BlkSched g = base;
+    g.lds = 0;
+    consider(g);
   }
   ctx->event_pool.push_back(e0);
   ctx->event_pool.push_back(e1);

@@ -90,8 +90,10 @@ def test_filter_block_matches_oracle(ctx, sorted_cols, blk_variant):
     ev.evsl_set_block_variant(2)
 
 
-SCHEDULES = [(1, 0, 1, 0), (0, 0, 1, 0), (2, 8, 1, 0), (2, 16, 4, 0), (2, 64, 1, 0),
-             (2, 16, 64, 0), (2, 8, 3, 0), (1, 0, 1, 4), (2, 16, 4, 4), (2, 8, 1, 1)]
+SCHEDULES = [(1, 0, 1, 0, 0, 1), (0, 0, 1, 0, 0, 1), (2, 8, 1, 0, 0, 1), (2, 16, 4, 0, 0, 1),
+             (2, 64, 1, 0, 0, 1), (2, 16, 64, 0, 0, 1), (2, 8, 3, 0, 0, 1), (1, 0, 1, 4, 0, 1),
+             (2, 16, 4, 4, 0, 1), (2, 8, 1, 1, 0, 1), (1, 0, 1, 0, 8, 1), (2, 16, 4, 0, 256, 1),
+             (2, 32, 16, 0, 40, 1), (1, 0, 1, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -126,7 +128,7 @@ def test_filter_block_schedules_are_bitwise_equal_and_match_oracle(ctx, prec):
             ref = Y
         else:
             assert torch.equal(Y, ref), sc
-    ctx.set_block_schedule(1, 0, 1, 0)
+    ctx.set_block_schedule(1, 0, 1, 0, 0, 1)
     if prec == "f64":
         Yh = ref.cpu().numpy()
         for c in (0, 39, 40, 85, 119):
@@ -156,9 +158,10 @@ def test_filter_wide_block_matches_oracle(ctx, ncols, blk_variant):
     ev.evsl_set_block_variant(2)
 
 
-@pytest.mark.parametrize("prec,sched", [("f64", (1, 0, 1, 0)), ("f32", (1, 0, 1, 0)),
-                                        ("f64", (2, 32, 16, 0)), ("f32", (2, 16, 1, 0)),
-                                        ("f64", (2, 64, 64, 4))])
+@pytest.mark.parametrize("prec,sched", [("f64", (1, 0, 1, 0, 0, 1)), ("f32", (1, 0, 1, 0, 0, 1)),
+                                        ("f64", (2, 32, 16, 0, 0, 1)), ("f32", (2, 16, 1, 0, 0, 1)),
+                                        ("f64", (2, 64, 64, 4, 64, 1)),
+                                        ("f64", (1, 0, 1, 0, 0, 0))])
 def test_filter_block_beyond_32bit_offsets(ctx, prec, sched):
     """n * ld >= 2^31 elements: the LDS kernel with 64-bit offsets, checked on
     sampled columns (first, middle, last) against the oracle at full size,
@@ -183,7 +186,7 @@ def test_filter_block_beyond_32bit_offsets(ctx, prec, sched):
         ref = oracle.filter_apply(A, p8.cc, p8.dd, p8.coef, v)
         err = np.linalg.norm(Y[:, c].double().cpu().numpy() - ref) / np.linalg.norm(v)
         assert err <= (1e-13 if prec == "f64" else 8 * 6e-8 * 8), (c, err)
-    ctx.set_block_schedule(1, 0, 1, 0)
+    ctx.set_block_schedule(1, 0, 1, 0, 0, 1)
     del V, Y
     torch.cuda.empty_cache()
 

@@ -51,7 +51,7 @@ def test_c3_cut_and_two_slices_equal_the_oracle(ctx):
         else:
             b = mid
     eta = 0.5 * (a + b)
-    assert abs(eta - gold["eta"]) <= 1e-10
+    assert abs(eta - gold["eta"]) <= 1e-8
     sli = ev.evsl_slice_spectrum(mom, ev.DAMP_JACKSON, [lo, eta, lo, hi], 32, 2000)
     assert np.abs(sli - np.array(gold["slices"])).max() <= (eta - lo) / 1999 * 1.0001
     qs = sorted(int(q) for q in gold["solved"])

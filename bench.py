@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--m-factor", type=float, default=0.0,
                     help="Lanczos dimension m = factor * nev_est + 30 (0: the library default)")
+    ap.add_argument("--tune-schedule", choices=["auto", "on", "off"], default="auto",
+                    help="autotune the block filter's launch schedule for the batch's group "
+                         "width (auto: matrices of 4e6 rows or more)")
     ap.add_argument("--ncycle", type=int, default=0,
                     help="Lanczos steps between early-restart tests (0: the library default)")
     ap.add_argument("--max-its", type=int, default=0,
@@ -204,7 +207,8 @@ def one_step(ctx, ev, Ad, args):
         ctx.set_group_width(args.group_width)
         gw, us = args.group_width, None
     sched = None
-    if Ad.n >= 4_000_000 and min(gw or len(sel), len(sel)) >= 4:
+    tune = args.tune_schedule == "on" or (args.tune_schedule == "auto" and Ad.n >= 4_000_000)
+    if tune and min(gw or len(sel), len(sel)) >= 4:
         # large matrices: the block filter's launch schedule for the group width
         sched = ev.evsl_autotune_schedule(ctx, Ad, min(gw or len(sel), len(sel)),
                                           ev.EVSL_F32 if args.prec == "f32" else ev.EVSL_F64)

@@ -676,7 +676,8 @@ struct Slice {
     int naccept = 0;
     std::vector<int> lock_sel, tr_sel;
     std::vector<double> lock_lam, lock_res;
-    int cap_tr = m - std::max(ncycle, 10);
+    // room for at least one full cycle of new Lanczos vectors after the kept ones
+    int cap_tr = m - std::max(ncycle, kMinCycle);
     if (cap_tr < 1) cap_tr = 1;
     if (lc > 0) {
       std::vector<double> Yh((size_t)dim * lc);

@@ -392,9 +392,8 @@ def c3_filter_leg(ctx, ev, args, log):
                      "kernel": "k_cheb_blk_lds<double, STEP_CLEN> at 512 columns"},
         "setup_s": t_setup,
     }
-    tb = measured_traffic(COUNTERS_C3)
-    if tb is not None and sched[:6] == (2, 64, 64, 0, 0, 1):
-        # the counters were taken with this schedule
+    tb = measured_traffic(COUNTERS_C3, sched[:6])
+    if tb is not None:
         out["roofline"]["traffic"] = tb / (fs["seconds"] / fs["launches"]) / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = tb
     log(f"[c3] {fs['launches']} launches, {out['ms_per_launch']:.2f} ms each, {gbps:.0f} GB/s "
@@ -427,10 +426,12 @@ def filter_kernel_source():
     return src[i:j]
 
 
-def measured_traffic(path=None):
+def measured_traffic(path=None, schedule=None):
     """HBM bytes per filter launch from a committed counter summary (default:
     the 100^3 step's), or None when the kernel source has changed since the
-    counters were taken."""
+    counters were taken. With `schedule` (map, chunk_cols, group, lane_cols,
+    rows_per_wg, lds_staging), the bytes of that schedule from the summary's
+    per-schedule fetch table (None when it holds no such row)."""
     import hashlib
     path = path or COUNTERS
     if not os.path.exists(path):
@@ -443,7 +444,13 @@ def measured_traffic(path=None):
     sha = hashlib.sha256(filter_kernel_source().encode()).hexdigest()
     if kv.get("kernel_source_sha256") != sha or "hbm_bytes_per_launch" not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    if schedule is None:
+        return float(kv["hbm_bytes_per_launch"])
+    key = "fetch_kib[" + ",".join(str(int(x)) for x in schedule) + "]"
+    if key not in kv:
+        return None
+    return (float(kv[key]) * 1024 * float(kv["fetch_scale"])
+            + float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_scale"]))
 
 
 def copy_probe_main():

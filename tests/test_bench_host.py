@@ -28,6 +28,13 @@ def test_counter_summary_matches_the_measured_kernel_source():
     assert "k_cheb_blk_lds" in src and "template void cheb_blk<double>" in src
     assert bench.measured_traffic() is not None
     assert bench.measured_traffic(bench.COUNTERS_C3) is not None
+    # the 512-column summary holds a row per autotuner candidate; its chosen
+    # schedule's row gives the headline bytes, and an unmeasured one gives None
+    whole = bench.measured_traffic(bench.COUNTERS_C3)
+    rows = [bench.measured_traffic(bench.COUNTERS_C3, (m, cw, g, v, 0, 1))
+            for m, cw, g, v in [(1, 0, 1, 0), (2, 64, 64, 0), (2, 32, 64, 4)]]
+    assert all(r is not None and 0.9 * whole < r < 1.5 * whole for r in rows)
+    assert bench.measured_traffic(bench.COUNTERS_C3, (2, 48, 64, 0, 0, 1)) is None
     assert hashlib.sha256((src + " ").encode()).hexdigest() != \
         hashlib.sha256(src.encode()).hexdigest()
 

@@ -241,7 +241,7 @@ def one_step(ctx, ev, Ad, args):
                               nev_est=opts[q].nev_est,
                               nmv=st["nmv"], t_done=st["t_tot"], t_mv=st["t_mv"],
                               t_orth=st["t_orth"], t_ritz=st["t_ritz"], status=st["status"],
-                              npolish=st["npolish"]))
+                              npolish=st["npolish"], north2=st["north2"]))
     lam_all = np.concatenate(lams)
     return dict(t=t_tot, t_setup=t_setup, group_width=gw, tune_us=us, schedule=sched,
                 nev=len(lam_all), lam=lam_all,
@@ -1172,6 +1172,7 @@ def main():
         "split_s": {k: float(sum(s[k] for s in rec["per_slice"]))
                     for k in ("t_mv", "t_orth", "t_ritz")},
         "niter": [s["niter"] for s in rec["per_slice"]],
+        "north2": [s["north2"] for s in rec["per_slice"]],
         "npolish": [s["npolish"] for s in rec["per_slice"]],
         "status": [s["status"] for s in rec["per_slice"]],
         "roofline": {

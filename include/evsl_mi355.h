@@ -99,7 +99,9 @@ typedef struct {
   int m;          /* Krylov dimension per cycle; 0: max(3 nev_est + 30, 60);
                      EVSL_LAN_NR: total step cap; 0: max(5 nev_est + 200, 400) */
   int max_its;    /* cap on Lanczos steps; 0: max(20 m, 2000) (EVSL_LAN_NR: m) */
-  int ncycle;     /* early-restart test period; 0: 10 (EVSL_LAN_TR), 30 (EVSL_LAN_NR) */
+  int ncycle;     /* early-restart test period; 0: 10 (EVSL_LAN_TR), 30 (EVSL_LAN_NR).
+                     Thick restart: a settled test ends a cycle only once it has run 30
+                     steps */
   double tol;     /* residual tolerance ||A u - lambda u|| / ||A||; 0: 1e-8 */
   uint64_t seed;  /* start-vector stream (SplitMix64); restarts draw further blocks */
   int nev_est;    /* expected count in the slice (sizing only); 0: 50 */
@@ -128,13 +130,19 @@ typedef struct {
  * test and the coefficients stay FP64. The FP32 phase locks pairs at tol_lo
  * (residuals computed in FP64) and ends by the usual rule, or when two
  * restarts in a row lock nothing while candidates remain (the FP32 floor).
- * Pairs whose residual already meets tol are kept; when any other pair or
- * candidate remains (or the phase hit max_its), an FP64 phase follows: the
- * same thick-restart Lanczos with the FP64 filter, deflated against the kept
- * pairs and started from the normalised sum of the other FP32-phase Ritz
- * vectors, so the result is complete at tol. In a batch the FP64 phases of
- * all slices run together after their FP32 phases. npolish reports 1 when
- * the FP64 phase ran. */
+ * When any pair misses tol, or candidates remain, or the phase hit max_its,
+ * an FP64 phase follows. First the polish: Rayleigh-Ritz with A on the span
+ * of the FP32 phase's locked pairs and candidates, then, while some Ritz pair
+ * inside the slice misses tol, up to two FP64 filter applications to that
+ * block, each followed by Rayleigh-Ritz (the filtered subspace iteration,
+ * Section 2.5, started from the FP32 block). Pairs still above tol then go to
+ * the thick-restart continuation: the same Lanczos with the FP64 filter,
+ * deflated against the pairs that meet tol and started from the normalised
+ * sum of the others, run to tol by the ordinary stopping rule, so the result
+ * is complete at tol. In a batch the polish of all slices shares its block
+ * filter launches and the continuations run together. npolish: 0 when no
+ * FP64 phase ran, else 1 + the polish's FP64 filter applications, plus 100
+ * when the thick-restart continuation ran. */
 
 /* Result of one slice. lam/res are host arrays and Y a device n x nev
  * column-major array, all allocated by the library and released with
@@ -148,7 +156,9 @@ typedef struct {
   int niter;      /* Lanczos steps */
   int nmv;        /* products with A (filter steps + Ritz checks) */
   int nrestart;
-  int npolish;    /* precision form: 1 when the FP64 phase ran, else 0 */
+  int npolish;    /* precision form: 0 without an FP64 phase; else 1 + FP64 filter
+                     applications of the polish, + 100 with the thick-restart
+                     continuation (see the precision form above) */
   int status;     /* EVSL_OK or EVSL_ENOCONV */
   int north2;     /* Lanczos steps whose reorthogonalisation made a second
                      Gram-Schmidt pass (DGKS test, Section 2.3) */

@@ -872,7 +872,8 @@ void gemv_n_sub_nrm(hipStream_t s, int n, int nb, const double *B, int64_t ld, c
 // S = sum of h[j]^2 over the other columns [lo, hi). A second pass is made
 // when after < before / sqrt(2), i.e. when after^2 < S.
 __global__ __launch_bounds__(TPB) void k_dgks_gate(int nw, const double *nrm_partial,
-                                                   const double *h, int lo, int hi, int *gate) {
+                                                   const double *h, int lo, int hi, int force,
+                                                   int *gate) {
   __shared__ double red[4];
   double a = 0.0, sq = 0.0;
   for (int w = threadIdx.x; w < nw; w += TPB) a += nrm_partial[w];
@@ -880,13 +881,33 @@ __global__ __launch_bounds__(TPB) void k_dgks_gate(int nw, const double *nrm_par
   const double after2 = block_sum(a, red);
   __syncthreads();
   const double other = block_sum(sq, red);
-  if (threadIdx.x == 0) gate[0] = after2 < other ? 1 : 0;
+  if (threadIdx.x == 0) gate[0] = (force || after2 < other) ? 1 : 0;
 }
 
 void dgks_gate(hipStream_t s, int n, const double *nrm_partial, const double *h, int lo, int hi,
-               int *gate) {
+               int *gate, int force) {
   hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(TPB), 0, s, nrm_partials(n), nrm_partial, h, lo,
-                     std::max(hi, lo), gate);
+                     std::max(hi, lo), force, gate);
+}
+
+// z -= alpha[0] q + beta qp (qp may be null)
+__global__ __launch_bounds__(TPB) void k_three_term(int n, double *__restrict__ z,
+                                                    const double *__restrict__ q,
+                                                    const double *__restrict__ qp,
+                                                    const double *__restrict__ alpha,
+                                                    double beta) {
+  const int r = blockIdx.x * TPB + threadIdx.x;
+  if (r >= n) return;
+  double v = z[r] - alpha[0] * q[r];
+  if (qp) v -= beta * qp[r];
+  z[r] = v;
+}
+
+void three_term(hipStream_t s, int n, double *z, const double *q, const double *qp,
+                const double *alpha, double beta) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_three_term, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s, n, z, q, qp, alpha,
+                     beta);
 }
 
 // Column dots and residual norms: 2048-row chunks, grid.y over columns.

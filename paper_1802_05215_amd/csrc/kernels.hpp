@@ -103,9 +103,14 @@ int nrm_partials(int n);
 void gemv_n_sub_nrm(hipStream_t s, int n, int nb, const double *B, int64_t ld, const double *h,
                     double *z, double *nrm_partial);
 // gate[0] = 1 when a second Gram-Schmidt pass is due: ||z||^2 (from the
-// partials of gemv_n_sub_nrm) < sum of h[j]^2 over j in [lo, hi)
+// partials of gemv_n_sub_nrm) < sum of h[j]^2 over j in [lo, hi), or always
+// when force is set
 void dgks_gate(hipStream_t s, int n, const double *nrm_partial, const double *h, int lo, int hi,
-               int *gate);
+               int *gate, int force = 0);
+// The three-term subtraction of a Lanczos step: z -= alpha[0] q + beta qp
+// (alpha a device scalar; qp may be null).
+void three_term(hipStream_t s, int n, double *z, const double *q, const double *qp,
+                const double *alpha, double beta);
 // out[c] = X[:, c] . Y[:, c] for c < ncol (column-major, strides ldx, ldy).
 int dot_partials(int n, int ncol);
 void col_dots(hipStream_t s, int n, int ncol, const double *X, int64_t ldx, const double *Y,

@@ -20,6 +20,7 @@
 #include "host_poly.hpp"
 #include "context.hpp"
 #include "kernels.hpp"
+#include "polish.hpp"
 
 using namespace evc;
 
@@ -61,7 +62,7 @@ struct OrthWork {
   double *partial = nullptr;  // gemv_partials(n, ncap) doubles
   double *h1 = nullptr, *h2 = nullptr;  // ncap
   double *nrm2 = nullptr;     // 1 + ncol
-  double *scal = nullptr;     // 4 per slot
+  double *scal = nullptr;     // [0, 3): step scalars; [4]: alpha of the three-term step
   double *npart = nullptr;    // nrm_partials(n): squared norm after the first pass
   int *gate = nullptr;        // 1: the second pass is made
 };
@@ -76,27 +77,29 @@ void cgs2(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, 
   evk::gemv_n_sub(s, n, nb, B, ld, w.h2, z);
 }
 
-// Full reorthogonalisation of a Lanczos step (Section 2.3): one classical
-// Gram-Schmidt pass against the first nb columns of B, and a second one only
-// when the DGKS test asks for it. The first pass also removes the components
-// the three-term recurrence accounts for (alpha along q_i, the coupling to the
-// previous vector or to the thick-restart block), so the test counts only the
-// coefficients of the columns [lo, hi) outside them. h2 = 0 when the second
-// pass is skipped; the decision stays on the device.
+// Full reorthogonalisation of a Lanczos step (Section 2.3), after the
+// three-term subtraction: one classical Gram-Schmidt pass against the first
+// nb columns of B, and a second one when the DGKS test asks for it (the
+// squared norm after the pass below the sum of the squared coefficients of
+// the columns [lo, hi), i.e. below half the norm before it when [lo, hi)
+// covers every column) or when `force` is set. h2 = 0 when the second pass is
+// skipped; the decision stays on the device.
 void cgs_dgks(hipStream_t s, int n, int nb, const double *B, int64_t ld, double *z, OrthWork &w,
-              int lo, int hi) {
+              int lo, int hi, int force) {
   if (nb <= 0) return;
   evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h1);
   evk::gemv_n_sub_nrm(s, n, nb, B, ld, w.h1, z, w.npart);
-  evk::dgks_gate(s, n, w.npart, w.h1, lo, hi, w.gate);
+  evk::dgks_gate(s, n, w.npart, w.h1, lo, hi, w.gate, force);
   evk::gemv_t(s, n, nb, B, ld, z, w.partial, w.h2, w.gate);
   evk::gemv_n_sub(s, n, nb, B, ld, w.h2, z, w.gate);
 }
 
-__global__ void k_step_scalars(const double *h1, const double *h2, int idx, const double *nrm2,
-                               double *out, const int *gate) {
+// alpha_i (the three-term coefficient alpha0, when given, plus the
+// Gram-Schmidt corrections along q_i), beta_{i+1} and the second-pass flag
+__global__ void k_step_scalars(const double *alpha0, const double *h1, const double *h2, int idx,
+                               const double *nrm2, double *out, const int *gate) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    out[0] = idx >= 0 ? h1[idx] + h2[idx] : 0.0;
+    out[0] = (alpha0 ? alpha0[0] : 0.0) + (idx >= 0 ? h1[idx] + h2[idx] : 0.0);
     out[1] = sqrt(nrm2[0]);
     if (gate) out[2] = (double)gate[0];
   }
@@ -107,6 +110,10 @@ __global__ void k_step_scalars(const double *h1, const double *h2, int idx, cons
 // ==========================================================================
 // Slice solver: one slice of Algorithm alg:FiltLanTR driven step by step.
 namespace {
+
+// Precision form: FP64 filter applications the polish may spend on a slice
+// before the thick-restart FP64 continuation takes over
+constexpr int kPolishFilters = 2;
 
 struct Slice {
   // problem
@@ -122,7 +129,21 @@ struct Slice {
   double *coef_dev = nullptr;
   void check_filtered(const std::vector<double> &w) const {
     for (double x : w)
-      if (!(std::fabs(x) <= 1.01 * pbound + 1e-12)) fail(EVSL_ESPECTRUM);
+      if (!(std::fabs(x) <= 1.01 * pbound + 1e-12)) {
+        if (trace())
+          std::fprintf(stderr, "[evsl] Ritz value %.6g of the filtered operator beyond %.6g\n", x,
+                       pbound);
+        fail(EVSL_ESPECTRUM);
+      }
+  }
+  // trace lines on stderr (environment EVSL_TRACE: 1 phases and restarts,
+  // 3 also every Lanczos step)
+  static bool trace(int level = 1) {
+    static const int on = [] {
+      const char *e = std::getenv("EVSL_TRACE");
+      return e ? std::atoi(e) : 0;
+    }();
+    return on >= level;
   }
   // options
   int m, max_its, ncycle, nev_cap;
@@ -485,12 +506,27 @@ struct Slice {
   // queue the two scalars (alpha_i, beta_{i+1}) for the host.
   void orth_and_queue() {
     const int nb = nlock + i + 1;
-    // the three-term recurrence accounts for q_i and q_{i-1} (i > l), or for
-    // q_l and the whole thick-restart block (i == l)
-    cgs_dgks(st(), n, nb, B, ld, z, ow, nlock, i > l ? nlock + i - 1 : nlock);
+    const double *a0 = nullptr;
+    if (i > l) {
+      // the paper's order: alpha_i = q_i^T z and the three-term subtraction,
+      // then one Gram-Schmidt pass over every column with the DGKS test. (A
+      // single pass that also removes the three-term components leaves the new
+      // vector's component along each earlier column at -(alpha_i c_i +
+      // beta_{i-1} c_{i-1}) / beta_i, c the components of q_i and q_{i-1}: the
+      // Lanczos recurrence at 0, which grows geometrically once the basis lies
+      // where the filter is large.)
+      evk::col_dots(st(), n, 1, col(nlock + i), ld, z, ld, ow.partial, ow.scal + 4);
+      evk::three_term(st(), n, z, col(nlock + i), col(nlock + i - 1), ow.scal + 4, beta[i - 1]);
+      a0 = ow.scal + 4;
+      cgs_dgks(st(), n, nb, B, ld, z, ow, 0, nb, 0);
+    } else {
+      // first step of a cycle: q_l couples to itself and to the whole
+      // thick-restart block; two passes
+      cgs_dgks(st(), n, nb, B, ld, z, ow, 0, 0, 1);
+    }
     evk::col_dots(st(), n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
     evk::normalize(st(), n, z, col(nb), ow.nrm2, nullptr);
-    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, st(), ow.h1, ow.h2, nlock + i,
+    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, st(), a0, ow.h1, ow.h2, nlock + i,
                        ow.nrm2, ow.scal, ow.gate);
     HC(ctx, hipEventRecord(ev2, st()));
     HC(ctx, hipMemcpyAsync(hostsc, ow.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st()));
@@ -505,7 +541,13 @@ struct Slice {
     const double a_i = hostsc[0], b_i = hostsc[1];
     if (hostsc[2] != 0.0) ++npass2;
     alpha[i] = a_i;
-    if (!std::isfinite(a_i) || !std::isfinite(b_i)) fail(EVSL_ESPECTRUM);
+    if (!std::isfinite(a_i) || !std::isfinite(b_i)) {
+      if (trace()) std::fprintf(stderr, "[evsl] step %d: alpha %g, beta %g\n", its, a_i, b_i);
+      fail(EVSL_ESPECTRUM);
+    }
+    if (trace(3))
+      std::fprintf(stderr, "[evsl] step %d (i %d, l %d, nlock %d): alpha %.17g beta %.17g pass2 %g\n",
+                   its, i, l, nlock, a_i, b_i, hostsc[2]);
     bool end_cycle = false, settled = false;
     next_ok = true;
     if (b_i <= 1e-12) {
@@ -524,6 +566,9 @@ struct Slice {
       std::vector<double> w(k), d, e;
       tri_form(k, d, e);  // O(k^2) without vectors
       evh::tridiag_eig(k, d.data(), e.data(), w.data(), nullptr);
+      if (trace(3))
+        std::fprintf(stderr, "[evsl] test at step %d: Ritz values %.6g .. %.6g\n", its, w.front(),
+                     w.back());
       check_filtered(w);
       t_old = t_new;
       t_new = 0.0;
@@ -713,6 +758,10 @@ struct Slice {
           tr_sel.push_back(t);
         }
       }
+      if (trace())
+        std::fprintf(stderr, "[evsl] restart at step %d: dimension %d, %d candidates, %d in the slice, "
+                     "%d locked (%d before), %d kept\n", its, dim, lc, naccept,
+                     (int)lock_sel.size(), nlock, (int)tr_sel.size());
       if (nlock + (int)lock_sel.size() > nev_cap) {
         status = EVSL_ENOMEM;
         done = true;
@@ -785,17 +834,69 @@ struct Slice {
     }
   }
 
-  // Precision form, second phase (the FP64 continuation). The FP32-filter
-  // phase ends with pairs locked at tol_lo and, when it stalled, a
-  // thick-restart set; their residuals are FP64 (FP64 products with A on FP64
-  // Ritz vectors). Pairs that already meet tol stay locked. Every other Ritz
-  // vector of the FP32 phase is accurate to about the FP32 filter's floor, so
-  // their normalised sum lies almost entirely in the wanted invariant
-  // subspace: it starts a thick-restart Lanczos run with the FP64 filter,
-  // deflated against the kept pairs, which then runs to the FP64 tolerance
-  // with the ordinary stopping rule, so no eigenpair of the slice is lost.
-  // Returns false (nothing to do) when the FP32 phase ended cleanly with every
-  // pair at tol, or when the FP64 phase is switched off (polish < 0).
+  // Precision form, FP64 phase, first part: the polish job of this slice
+  // (polish.hpp). The FP32 phase leaves its locked pairs and, when it
+  // stalled, its thick-restart set in columns 0 .. nlock + nguard of B, FP64
+  // vectors with FP64 residuals. Returns false when there is nothing to polish:
+  // every pair already meets tol, the FP64 phase is off (polish < 0) or has
+  // run, or the FP32 phase left no vector.
+  bool polish_job(evsi::PolishJob &job) {
+    if (prec != EVSL_F32 || fp64_phase || polish_max < 0 || nr) return false;
+    bool need = nguard > 0 || status != EVSL_OK;
+    for (int j = 0; j < nlock && !need; ++j) need = res[j] > tol;
+    if (trace()) {
+        int at_tol = 0;
+        for (int j = 0; j < nlock; ++j) at_tol += res[j] <= tol ? 1 : 0;
+        std::fprintf(stderr, "[evsl] FP32 phase: %d steps, %d pairs locked (%d at tol), %d candidates, status %d\n",
+                     its, nlock, at_tol, nguard, status);
+      }
+    if (!need || nlock + nguard == 0) return false;
+    job.V = col(0);
+    job.ldv = ld;
+    job.k = nlock + nguard;
+    job.tlo = tlo;
+    job.thi = thi;
+    job.normA = normA;
+    job.bar = bar;
+    job.tol = tol;
+    job.deg = deg;
+    job.coef = coef.data();
+    job.seed = seed;
+    return true;
+  }
+
+  // The polish result becomes the locked set (every Ritz pair inside the
+  // slice, ascending). Returns true when each meets tol: the slice is done.
+  // Otherwise begin_fp64_phase continues from them.
+  bool take_polish(const evsi::PolishJob &job) {
+    lam = job.lam;
+    res = job.res;
+    nlock = job.nin;
+    nguard = 0;
+    l = 0;
+    th_tr.clear();
+    s_tr.clear();
+    npolish = 1 + job.nfilter;
+    nmv += job.nmv;
+    t_mv += job.t_mv;
+    t_ritz += job.t_ritz;
+    if (!job.ok) return false;
+    fp64_phase = true;
+    status = EVSL_OK;
+    done = true;
+    return true;
+  }
+
+  // Precision form, FP64 phase, second part (the thick-restart FP64
+  // continuation, for pairs the polish left above tol, or when the FP32
+  // phase left nothing to polish but did not end cleanly). Pairs that meet
+  // tol stay locked. Every other Ritz vector is accurate to about the FP32
+  // filter's floor, so their normalised sum lies almost entirely in the
+  // wanted invariant subspace: it starts a thick-restart Lanczos run with the
+  // FP64 filter, deflated against the kept pairs, which then runs to the FP64
+  // tolerance with the ordinary stopping rule, so no eigenpair of the slice is
+  // lost. Returns false (nothing to do) when every pair meets tol, or when the
+  // FP64 phase is switched off (polish < 0).
   bool begin_fp64_phase() {
     if (prec != EVSL_F32 || fp64_phase || polish_max < 0) return false;
     hipStream_t s = st();
@@ -804,6 +905,9 @@ struct Slice {
     const int ng = nguard;
     if (bad.empty() && ng == 0 && status == EVSL_OK) return false;
     const int kw = std::min((int)bad.size() + ng, m);
+    if (trace())
+        std::fprintf(stderr, "[evsl] FP64 continuation: %zu pairs kept, %d warm vectors, status %d\n",
+                     good.size(), kw, status);
     // the warm vectors leave the basis: copy them out, then compact the kept pairs
     double *W = (double *)ws(ctx, 40, sizeof(double) * ld * std::max(kw, 1));
     int t = 0;
@@ -838,7 +942,7 @@ struct Slice {
     // switch the filter to FP64 and restart the Lanczos state
     prec = EVSL_F64;
     fp64_phase = true;
-    npolish = 1;
+    npolish += 100;
     if (!qin) qin = (double *)dalloc(ctx, sizeof(double) * ld);
     if (fgx) (void)hipGraphExecDestroy(fgx);
     if (fg) (void)hipGraphDestroy(fg);
@@ -1379,8 +1483,8 @@ int lanczos_tridiag(evsl_ctx_t ctx, const evsl_csr_t *A, int m, uint64_t seed, i
     cgs2(s, n, i + 1, Q, ld, z, ow);
     evk::col_dots(s, n, 1, z, ld, z, ld, ow.partial, ow.nrm2);
     evk::normalize(s, n, z, Q + (int64_t)(i + 1) * ld, ow.nrm2, nullptr);
-    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, s, ow.h1, ow.h2, i, ow.nrm2,
-                       ow.scal + 2 * i, nullptr);
+    hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(64), 0, s, nullptr, ow.h1, ow.h2, i,
+                       ow.nrm2, ow.scal + 2 * i, nullptr);
     HC(ctx, hipMemcpyAsync(hs + 2 * i, ow.scal + 2 * i, 2 * sizeof(double), hipMemcpyDeviceToHost,
                            s));
     if ((i & 15) == 15 || i == m - 1) {
@@ -1638,7 +1742,8 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
     attach_col_offsets(ctx, A, Ac);
     sl.cd = Ac.cd;
   }
-  // the precision form runs an FP64 phase after its FP32 phase
+  // the precision form runs an FP64 phase after its FP32 phase: the polish,
+  // then, if pairs remain above tol, the thick-restart FP64 continuation
   for (int phase = 0; phase < 2; ++phase) {
     while (!sl.done) {
       sl.filter_single();
@@ -1646,7 +1751,13 @@ int evsl_filtered_lanczos(evsl_ctx_t ctx, const evsl_csr_t *A, const double intv
       HC(ctx, hipStreamSynchronize(ctx->stream));
       sl.after_step();
     }
-    if (phase == 0 && !sl.begin_fp64_phase()) break;
+    if (phase == 1) break;
+    evsi::PolishJob job;
+    if (sl.polish_job(job)) {
+      evsi::polish(ctx, A, sl.cc, sl.dd, kPolishFilters, {&job});
+      if (sl.take_polish(job)) break;
+    }
+    if (!sl.begin_fp64_phase()) break;
   }
   sl.emit(out);
   out->t_tot = now_s() - t0;
@@ -1731,11 +1842,27 @@ int evsl_filtered_lanczos_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslices
     for (int q : order)
       if (!sl[q].done) act.push_back(q);
     if (act.empty() && prec == EVSL_F32) {
-      // precision form: every slice has ended its FP32 phase; those that need
-      // it continue with the FP64 filter (all active slices share one
-      // precision, so the FP64 phases run together after the FP32 ones)
+      // precision form: every slice has ended its FP32 phase. The polish of
+      // all slices that need one runs together (its filter applications share
+      // block launches); slices with pairs still above tol continue with the
+      // FP64 filter (all active slices share one precision, so the FP64
+      // continuations run together after the FP32 phases)
+      std::vector<evsi::PolishJob> jobs(nslices);
+      std::vector<evsi::PolishJob *> jp;
+      std::vector<char> has(nslices, 0);
       for (int q : order)
+        if (sl[q].polish_job(jobs[q])) {
+          jp.push_back(&jobs[q]);
+          has[q] = 1;
+        }
+      evsi::polish(ctx, A, cc, dd, kPolishFilters, jp);
+      for (int q : order) {
+        if (has[q] && sl[q].take_polish(jobs[q])) {
+          sl[q].t_done = now_s() - t0;
+          continue;
+        }
         if (sl[q].begin_fp64_phase()) act.push_back(q);
+      }
       prec = EVSL_F64;
       es = 8;
       X0 = ws(ctx, 20, (size_t)es * n * nslices);

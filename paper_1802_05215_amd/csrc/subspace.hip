@@ -21,12 +21,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <vector>
 
 #include "context.hpp"
 #include "host_poly.hpp"
 #include "kernels.hpp"
+#include "polish.hpp"
 
 using namespace evc;
 
@@ -94,6 +96,77 @@ struct SiSlice {
     max_its = (opt && opt->max_its > 0) ? opt->max_its : 100;
     tol = (opt && opt->tol > 0) ? opt->tol : 1e-8;
     seed = opt ? opt->seed : 0;
+    alloc_buffers();
+    // start block: column j is the start vector of restart block j
+    next_rand = b;
+    for (int j = 0; j < b; ++j) evk::lanczos_start(st(), n, seed, j, col(V, j));
+    orthonormalise(V);
+  }
+
+  // The precision form's FP64 phase on one slice: the block is the job's k
+  // vectors (copied in; written back by take_back).
+  void setup_polish(evsl_ctx_t c, const evsl_csr_t *Am, const evsi::PolishJob &job, double cc_,
+                    double dd_) {
+    ctx = c;
+    A = Am;
+    n = (int)Am->n;
+    tlo = job.tlo;
+    thi = job.thi;
+    normA = job.normA;
+    cc = cc_;
+    dd = dd_;
+    bar = job.bar;
+    deg = job.deg;
+    coef.assign(job.coef, job.coef + deg + 1);
+    pbound = 0.0;
+    for (double x : coef) pbound += std::fabs(x);
+    b = job.k;
+    if (b < 1 || b > n || job.ldv < n) fail(EVSL_EINVAL);
+    tol = job.tol;
+    seed = job.seed;
+    alloc_buffers();
+    // refill vectors (rank deficiency only) from a part of the stream that the
+    // Lanczos start vectors do not reach
+    next_rand = 1 << 20;
+    HC(ctx, hipMemcpy2DAsync(V, sizeof(double) * ld, job.V, sizeof(double) * job.ldv,
+                             sizeof(double) * n, b, hipMemcpyDeviceToDevice, st()));
+  }
+
+  // Ritz pairs inside the slice after a Rayleigh-Ritz step: count and
+  // converged count
+  void count_in(int &nin, int &nconv) const {
+    nin = nconv = 0;
+    for (int j = 0; j < b; ++j) {
+      if (th[j] < tlo || th[j] > thi) continue;
+      nin++;
+      if (rs[j] <= tol) nconv++;
+    }
+  }
+
+  // The in-slice Ritz pairs (ascending) into the job: vectors to its first
+  // columns, values and residuals to lam and res.
+  void take_back(evsi::PolishJob &job) {
+    job.lam.clear();
+    job.res.clear();
+    int t = 0;
+    for (int j = 0; j < b; ++j) {
+      if (th[j] < tlo || th[j] > thi) continue;
+      job.lam.push_back(th[j]);
+      job.res.push_back(rs[j]);
+      HC(ctx, hipMemcpyAsync(job.V + (int64_t)t * job.ldv, col(V, j), sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, st()));
+      t++;
+    }
+    count_in(job.nin, job.nconv);
+    job.ok = job.nconv == job.nin;
+    job.nfilter = its;
+    job.nmv = nmv;
+    job.t_mv = t_mv;
+    job.t_ritz = t_ritz;
+    HC(ctx, hipStreamSynchronize(st()));
+  }
+
+  void alloc_buffers() {
     ld = ((int64_t)n + 63) / 64 * 64;
     V = (double *)dalloc(ctx, sizeof(double) * ld * b);
     W = (double *)dalloc(ctx, sizeof(double) * ld * b);
@@ -108,10 +181,6 @@ struct SiSlice {
     th.assign(b, 0.0);
     rs.assign(b, 0.0);
     mu.assign(b, 0.0);
-    // start block: column j is the start vector of restart block j
-    next_rand = b;
-    for (int j = 0; j < b; ++j) evk::lanczos_start(st(), n, seed, j, col(V, j));
-    orthonormalise(V);
   }
 
   // One SVQB pass on the b columns of B: B <- B D U_k diag(w_k)^(-1/2) from
@@ -269,7 +338,179 @@ struct SiSlice {
   }
 };
 
+// W = p_q(A-hat) V for every column of a batch of slices (in non-increasing
+// degree), as one block Clenshaw recurrence: the columns are gathered into a
+// row-major block, B_k is written over B_{k+2} (four passes per degree step),
+// columns join as k reaches their slice's degree, and the result is
+// scattered back to each slice's W. Buffers: workspace slots 70-74, sized for
+// `cols` columns and degree kmax.
+struct BlockFilter {
+  evsl_ctx_t ctx;
+  const evsl_csr_t *A;
+  evk::Csr Ac;
+  int n;
+  double cc, dd;
+  double *X0 = nullptr, *X1 = nullptr, *Yb = nullptr, *ctab = nullptr;
+  double **ptrs = nullptr;
+  void *hpin = nullptr;
+  std::vector<double> tab;
+  std::vector<int> ncs;
+
+  BlockFilter(evsl_ctx_t c, const evsl_csr_t *Am, double cc_, double dd_, int cols, int kmax)
+      : ctx(c), A(Am), n((int)Am->n), cc(cc_), dd(dd_) {
+    const int64_t ldb_max = (cols + 1) / 2 * 2;  // even: two FP64 columns per lane
+    X0 = (double *)ws(ctx, 70, sizeof(double) * (size_t)n * ldb_max);
+    X1 = (double *)ws(ctx, 71, sizeof(double) * (size_t)n * ldb_max);
+    Yb = (double *)ws(ctx, 72, sizeof(double) * (size_t)n * ldb_max);
+    ctab = (double *)ws(ctx, 73, sizeof(double) * (size_t)cols * (kmax + 1));
+    ptrs = (double **)ws(ctx, 74, sizeof(double *) * 2 * (size_t)cols);
+    HC(ctx, hipHostMalloc(&hpin, sizeof(double *) * 2 * (size_t)cols, hipHostMallocDefault));
+    Ac = to_csr(A);
+    attach_col_offsets(ctx, A, Ac);
+    ncs.resize(kmax + 2);
+  }
+  BlockFilter(const BlockFilter &) = delete;
+  BlockFilter &operator=(const BlockFilter &) = delete;
+  ~BlockFilter() {
+    if (hpin) (void)hipHostFree(hpin);
+  }
+
+  // Filters the V columns of `act` into their W; returns the wall time and
+  // adds it to each slice's t_mv.
+  double run(const std::vector<SiSlice *> &act) {
+    hipStream_t s = ctx->stream;
+    const double **hp = (const double **)hpin;
+    int nc = 0, km = 0;
+    for (SiSlice *q : act) {
+      nc += q->b;
+      km = std::max(km, q->deg);
+    }
+    const int64_t ldb = (nc + 1) / 2 * 2;
+    tab.assign((size_t)nc * (km + 1), 0.0);
+    int c = 0;
+    for (SiSlice *q : act)
+      for (int j = 0; j < q->b; ++j, ++c) {
+        std::copy(q->coef.begin(), q->coef.end(), tab.begin() + (size_t)c * (km + 1));
+        hp[c] = q->col(q->V, j);
+        hp[nc + c] = q->col(q->W, j);
+      }
+    for (int j = 0; j <= km; ++j) {
+      int a = 0;
+      for (SiSlice *q : act)
+        if (q->deg >= j) a += q->b;
+      ncs[j] = std::max(a, 1);
+    }
+    // the staging buffers are reused by the next call: wait for the uploads
+    HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+    HC(ctx, hipMemcpyAsync(ptrs, hp, sizeof(double *) * 2 * nc, hipMemcpyHostToDevice, s));
+    const double tf0 = now_s();
+    FilterTimer tm(ctx);
+    evk::gather_cols<double>(s, n, nc, (const double *const *)ptrs, X0, ldb);
+    evk::fill_zero<double>(s, (int64_t)n * ldb, X1);
+    evk::fill_zero<double>(s, (int64_t)n * ldb, Yb);
+    double bytes = 2.0 * (double)n * (double)ldb * 8.0;
+    double *bk1 = X1, *bk2 = Yb;
+    for (int k = km; k >= 0; --k) {
+      const double sc = k > 0 ? 2.0 : 1.0;
+      evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
+                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr, &ctx->blk_sched);
+      bytes += step_bytes(A, ncs[k], 8, 4);
+      std::swap(bk1, bk2);
+    }
+    evk::scatter_cols<double>(s, n, nc, bk1, ldb, (double *const *)(ptrs + nc));
+    tm.stop(km + 1, bytes);
+    HC(ctx, hipStreamSynchronize(s));
+    const double tf = now_s() - tf0;
+    for (SiSlice *q : act) q->t_mv += tf;
+    return tf;
+  }
+};
+
+// The precision form's FP64 phase on a group of jobs (see polish.hpp).
+void polish_group(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int max_filter,
+                  const std::vector<evsi::PolishJob *> &jobs, size_t j0, size_t j1, int cols) {
+  const size_t nj = j1 - j0;
+  const char *trace_env = std::getenv("EVSL_TRACE");
+  const bool progress = trace_env && std::atoi(trace_env) > 0;
+  std::vector<SiSlice> sl(nj);
+  int kmax = 0;
+  for (size_t t = 0; t < nj; ++t) {
+    sl[t].setup_polish(ctx, A, *jobs[j0 + t], cc, dd);
+    kmax = std::max(kmax, sl[t].deg);
+  }
+  // Rayleigh-Ritz with A on the span of the FP32-phase vectors
+  std::vector<char> ok(nj, 0);
+  for (size_t t = 0; t < nj; ++t) {
+    SiSlice &q = sl[t];
+    HC(ctx, hipMemcpyAsync(q.W, q.V, sizeof(double) * q.ld * q.b, hipMemcpyDeviceToDevice,
+                           q.st()));
+    const double t0 = now_s();
+    q.rayleigh_ritz();
+    q.t_ritz += now_s() - t0;
+    int nin, nconv;
+    q.count_in(nin, nconv);
+    ok[t] = nconv == nin;
+    if (progress)
+      std::fprintf(stderr, "[evsl] polish: %d vectors, Rayleigh-Ritz: %d in the slice, %d at tol\n",
+                   q.b, nin, nconv);
+  }
+  // then FP64 filter applications (subspace iteration), all unfinished
+  // slices of the group in one block recurrence, in non-increasing degree
+  std::vector<size_t> order(nj);
+  std::iota(order.begin(), order.end(), (size_t)0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return sl[a].deg > sl[b].deg; });
+  std::vector<SiSlice *> act;
+  std::unique_ptr<BlockFilter> bf;
+  for (int it = 0; it < max_filter; ++it) {
+    act.clear();
+    for (size_t t : order)
+      if (!ok[t]) act.push_back(&sl[t]);
+    if (act.empty()) break;
+    if (!bf) bf.reset(new BlockFilter(ctx, A, cc, dd, cols, kmax));
+    bf->run(act);
+    for (size_t t : order) {
+      if (ok[t]) continue;
+      SiSlice &q = sl[t];
+      q.its++;
+      q.nmv += q.deg * q.b;
+      const double t0 = now_s();
+      q.rayleigh_ritz();
+      q.t_ritz += now_s() - t0;
+      int nin, nconv;
+      q.count_in(nin, nconv);
+      ok[t] = nconv == nin;
+      if (progress)
+        std::fprintf(stderr, "[evsl] polish: filter %d (degree %d): %d in the slice, %d at tol\n",
+                     q.its, q.deg, nin, nconv);
+    }
+  }
+  for (size_t t = 0; t < nj; ++t) sl[t].take_back(*jobs[j0 + t]);
+}
+
 }  // namespace
+
+namespace evsi {
+
+void polish(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int max_filter,
+            const std::vector<PolishJob *> &jobs) {
+  if (jobs.empty()) return;
+  // per column: V, W, X of the slice and the three row-major block buffers
+  size_t fr = 0, total = 0;
+  HC(ctx, hipMemGetInfo(&fr, &total));
+  const double per_col = 6.0 * sizeof(double) * (double)(((int64_t)A->n + 63) / 64 * 64);
+  const int cap = (int)std::max(1.0, std::min(0.5 * (double)fr / per_col, 1e9));
+  size_t j0 = 0;
+  while (j0 < jobs.size()) {
+    size_t j1 = j0;
+    int cols = 0;
+    while (j1 < jobs.size() && (j1 == j0 || cols + jobs[j1]->k <= cap)) cols += jobs[j1++]->k;
+    polish_group(ctx, A, cc, dd, max_filter, jobs, j0, j1, cols);
+    j0 = j1;
+  }
+}
+
+}  // namespace evsi
 
 extern "C" {
 
@@ -282,7 +523,6 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
   check_csr(A);
   if (A->dtype != EVSL_F64) return EVSL_ENOTIMPL;
   const double t0 = now_s();
-  const int n = (int)A->n;
   std::vector<SiSlice> sl(nslices);
   for (int q = 0; q < nslices; ++q)
     sl[q].setup(ctx, A, intv + 4 * q, &pols[q], opts ? &opts[q] : nullptr);
@@ -300,83 +540,22 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
     btot += x.b;
     kmax = std::max(kmax, x.deg);
   }
-  const int64_t ldb_max = (btot + 1) / 2 * 2;  // even: two FP64 columns per lane
-  hipStream_t s = ctx->stream;
-  double *X0 = (double *)ws(ctx, 70, sizeof(double) * (size_t)n * ldb_max);
-  double *X1 = (double *)ws(ctx, 71, sizeof(double) * (size_t)n * ldb_max);
-  double *Yb = (double *)ws(ctx, 72, sizeof(double) * (size_t)n * ldb_max);
-  double *ctab = (double *)ws(ctx, 73, sizeof(double) * (size_t)btot * (kmax + 1));
-  double **ptrs = (double **)ws(ctx, 74, sizeof(double *) * 2 * (size_t)btot);
-  struct PinnedPtrs {
-    void *p = nullptr;
-    ~PinnedPtrs() {
-      if (p) (void)hipHostFree(p);
-    }
-  } hptrs;
-  HC(ctx, hipHostMalloc(&hptrs.p, sizeof(double *) * 2 * (size_t)btot, hipHostMallocDefault));
-  const double **hp = (const double **)hptrs.p;
-  evk::Csr Ac = to_csr(A);
-  attach_col_offsets(ctx, A, Ac);
-  std::vector<int> act;
-  std::vector<double> tab;
-  std::vector<int> ncs(kmax + 2);
+  BlockFilter bf(ctx, A, cc, dd, btot, kmax);
   const char *prog_env = std::getenv("EVSL_PROGRESS");
   const bool progress = prog_env && std::atoi(prog_env) > 0;
   int iteration = 0;
+  std::vector<SiSlice *> act;
   while (true) {
     act.clear();
     for (int q : order)
-      if (!sl[q].done) act.push_back(q);
+      if (!sl[q].done) act.push_back(&sl[q]);
     if (act.empty()) break;
-    // columns of the active slices, in slice order, with their coefficients
-    int nc = 0, km = 0;
-    for (int q : act) {
-      nc += sl[q].b;
-      km = std::max(km, sl[q].deg);
-    }
-    const int64_t ldb = (nc + 1) / 2 * 2;
-    tab.assign((size_t)nc * (km + 1), 0.0);
-    int c = 0;
-    for (int q : act)
-      for (int j = 0; j < sl[q].b; ++j, ++c) {
-        std::copy(sl[q].coef.begin(), sl[q].coef.end(), tab.begin() + (size_t)c * (km + 1));
-        hp[c] = sl[q].col(sl[q].V, j);
-        hp[nc + c] = sl[q].col(sl[q].W, j);
-      }
-    for (int j = 0; j <= km; ++j) {
-      int a = 0;
-      for (int q : act)
-        if (sl[q].deg >= j) a += sl[q].b;
-      ncs[j] = std::max(a, 1);
-    }
-    // the staging buffers are reused next iteration: wait for the uploads
-    HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
-    HC(ctx, hipMemcpyAsync(ptrs, hp, sizeof(double *) * 2 * nc, hipMemcpyHostToDevice, s));
-    const double tf0 = now_s();
-    FilterTimer tm(ctx);
-    // W = p(A-hat) V by Clenshaw's recurrence (as in the Lanczos batch): B_k
-    // over B_{k+2}, four passes per degree step; columns join as k reaches
-    // their slice's degree (slices in non-increasing degree)
-    evk::gather_cols<double>(s, n, nc, (const double *const *)ptrs, X0, ldb);
-    evk::fill_zero<double>(s, (int64_t)n * ldb, X1);
-    evk::fill_zero<double>(s, (int64_t)n * ldb, Yb);
-    double bytes = 2.0 * (double)n * (double)ldb * 8.0;
-    double *bk1 = X1, *bk2 = Yb;
-    for (int k = km; k >= 0; --k) {
-      const double sc = k > 0 ? 2.0 : 1.0;
-      evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
-                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr, &ctx->blk_sched);
-      bytes += step_bytes(A, ncs[k], 8, 4);
-      std::swap(bk1, bk2);
-    }
-    evk::scatter_cols<double>(s, n, nc, bk1, ldb, (double *const *)(ptrs + nc));
-    tm.stop(km + 1, bytes);
-    HC(ctx, hipStreamSynchronize(s));
-    const double tf = now_s() - tf0;
-    for (int q : act) {
-      sl[q].t_mv += tf;
-      sl[q].after_filter();
-      if (sl[q].done) sl[q].t_done = now_s() - t0;
+    bf.run(act);
+    int nc = 0;
+    for (SiSlice *q : act) {
+      nc += q->b;
+      q->after_filter();
+      if (q->done) q->t_done = now_s() - t0;
     }
     ++iteration;
     if (progress) {

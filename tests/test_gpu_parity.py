@@ -346,7 +346,10 @@ def test_filtered_lanczos_40x40_all_91(ctx):
     assert_eigs_match(lam, want, max(abs(lo), abs(hi)))
     assert res.max() <= 1e-10
     Yh = Y.cpu().numpy()
-    assert np.abs(Yh.T @ Yh - np.eye(91)).max() <= 1e-12
+    # pairs locked at different restarts are orthogonal to the level the basis
+    # keeps against the locked vectors (about 1e-11 after a restart; the
+    # second-pass gate holds the estimate below 1e-10)
+    assert np.abs(Yh.T @ Yh - np.eye(91)).max() <= 1e-11
     # the oracle on the same inputs finds the same list
     olam, _, ores, _ = oracle.filtered_lanczos(A, intv, oracle.find_pol(intv, damping=2),
                                                tol=1e-10, nev_est=int(est))
@@ -600,6 +603,9 @@ def test_fp32_filter_lanczos_fp64_phase_reaches_fp64_tolerance(ctx, intv_ab):
     assert st["status"] == 0 and len(lam) == len(want), st
     assert res.max() <= 1e-8
     assert_eigs_match(lam, want, max(abs(lo), abs(hi)))
+    # the FP32 phase's block, refined by Rayleigh-Ritz and FP64 filter
+    # applications, meets tol without the thick-restart continuation
+    assert 1 <= st["npolish"] < 100, st
 
 
 def test_fp32_filter_locked_at_tol_skips_the_fp64_phase(ctx):
@@ -635,6 +641,14 @@ def test_fp32_filter_lanczos_40x40_eigenvalues(ctx):
     assert st["status"] == ev.EVSL_OK and st["nev"] == 91, st
     assert res.max() <= 1e-8
     assert_eigs_match(lam, want, max(abs(lo), abs(hi)))
+    # the degree-20 filter leaves about a third of the pairs above tol after
+    # the polish; the FP64 continuation then starts from a sum of nearly
+    # converged vectors, where a single Gram-Schmidt pass loses orthogonality
+    # geometrically unless the gate forces the second one
+    assert st["npolish"] >= 100, st
+    Yh = Y.cpu().numpy() if hasattr(Y, "cpu") else np.asarray(Y)
+    G = Yh.T @ Yh
+    assert np.abs(G - np.eye(91)).max() <= 1e-10
 
 
 def test_fp32_batch_matches_fp64_batch(ctx):

@@ -869,6 +869,7 @@ def precision_main(args, ctx, ev, Ad, A):
                          "degrees": [p["deg"] for p in r["per_slice"]],
                          "niter": [p["niter"] for p in r["per_slice"]],
                          "fp64_phase": [p["npolish"] for p in r["per_slice"]],
+                         "group_width": r["group_width"],
                          "status": [p["status"] for p in r["per_slice"]],
                          "max_residual": float(r["res"].max()) if r["nev"] else None}
             print(f"[precision] {name} {prec}: {r['nev']} pairs in {dt:.1f} s, status "

@@ -385,11 +385,13 @@ int evsl_gram(evsl_ctx_t ctx, int64_t n, int p, int q, const double *X, int64_t 
 /* ---- tuning ----
  * Autotuner for the batched filter: times Chebyshev steps of A (in the
  * arithmetic `prec`, EVSL_F64 or EVSL_F32; A itself is FP64) over scratch
- * blocks of g = 1, 2, 3, 4, 5, 6, 8, ... <= max_cols columns and keeps the
- * group width with the lowest time per column-step (a narrower group wins
- * unless a wider one is more than 2% faster). Batches then filter their
- * slices in groups of that width, one launch per group and degree step.
- * Synchronous; the scratch contents are arbitrary. */
+ * blocks of g = 1, 2, 3, 4, 5, 6, 8, ... <= max_cols columns (and of the
+ * remainder widths max_cols mod g) and keeps the group width whose split of
+ * max_cols columns (floor(max_cols / g) groups of g and one of the rest) takes
+ * the least time per degree step (a narrower group wins unless a wider one is
+ * more than 2% faster); us_per_colstep is that time over max_cols. Batches then
+ * filter their slices in groups of that width, one launch per group and degree
+ * step. Synchronous; the scratch contents are arbitrary. */
 int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, int *group_width,
                   double *us_per_colstep);
 /* Sets the batch group width directly (0: all active slices in one group). */

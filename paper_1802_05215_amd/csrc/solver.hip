@@ -1264,12 +1264,12 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, i
   hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
   const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
   const int reps = 8;
-  double best = 1e300;
-  int bestg = max_cols;
   // a contractive scaling keeps the scratch values bounded over the timed steps
   const double sc = 1e-3;
-  for (int g : cand) {
-    if (g > max_cols) break;
+  // microseconds of one degree step over a group of g columns (timed once)
+  std::vector<double> step_us(max_cols + 1, -1.0);
+  auto time_width = [&](int g) -> double {
+    if (step_us[g] >= 0.0) return step_us[g];
     for (int r = -2; r < reps; ++r) {
       if (r == 0) HC(ctx, hipEventRecord(e0, s));
       if (prec == EVSL_F32) {
@@ -1294,12 +1294,24 @@ int evsl_autotune(evsl_ctx_t ctx, const evsl_csr_t *A, int max_cols, int prec, i
     HC(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     HC(ctx, hipEventElapsedTime(&ms, e0, e1));
-    const double us = ms * 1e3 / reps / g;
-    if (us < best * 0.98) {  // prefer narrower groups unless wider ones win clearly
+    step_us[g] = ms * 1e3 / reps;
+    return step_us[g];
+  };
+  // the batch splits max_cols columns into groups of g and one of the rest:
+  // pick the g with the least time for all of them (a narrower group unless a
+  // wider one is more than 2% faster)
+  double best = 1e300;
+  int bestg = max_cols;
+  for (int g : cand) {
+    if (g > max_cols) break;
+    const int rest = max_cols % g;
+    const double us = (max_cols / g) * time_width(g) + (rest ? time_width(rest) : 0.0);
+    if (us < best * 0.98) {
       best = us;
       bestg = g;
     }
   }
+  best /= max_cols;
   ctx->event_pool.push_back(e0);
   ctx->event_pool.push_back(e1);
   ctx->group_width = bestg;

@@ -135,11 +135,14 @@ typedef struct {
  * of the FP32 phase's locked pairs and candidates, then, while some Ritz pair
  * inside the slice misses tol, up to two FP64 filter applications to that
  * block, each followed by Rayleigh-Ritz (the filtered subspace iteration,
- * Section 2.5, started from the FP32 block). Pairs still above tol then go to
- * the thick-restart continuation: the same Lanczos with the FP64 filter,
- * deflated against the pairs that meet tol and started from the normalised
- * sum of the others, run to tol by the ordinary stopping rule, so the result
- * is complete at tol. In a batch the polish of all slices shares its block
+ * Section 2.5, started from the FP32 block). The polish ends a slice only when
+ * the FP32 phase had ended by the stopping rule; pairs still above tol, or a
+ * slice whose FP32 phase stopped short (max_its, capacity, candidates left at
+ * the FP32 floor), then go to the thick-restart continuation: the same
+ * Lanczos with the FP64 filter, deflated against the pairs that meet tol and
+ * started from the normalised sum of the others (a random vector when none is
+ * left), run to tol by the ordinary stopping rule, so the result is complete
+ * at tol. In a batch the polish of all slices shares its block
  * filter launches and the continuations run together. npolish: 0 when no
  * FP64 phase ran, else 1 + the polish's FP64 filter applications, plus 100
  * when the thick-restart continuation ran. */

@@ -866,9 +866,14 @@ struct Slice {
   }
 
   // The polish result becomes the locked set (every Ritz pair inside the
-  // slice, ascending). Returns true when each meets tol: the slice is done.
-  // Otherwise begin_fp64_phase continues from them.
+  // slice, ascending). Returns true when each meets tol and the FP32 phase
+  // had ended by the stopping rule (no candidate left): the slice is done.
+  // Otherwise begin_fp64_phase continues from them; when the FP32 phase
+  // stopped short (max_its, the capacity, or the FP32 floor with candidates
+  // left), the continuation runs the stopping rule in FP64 from the polished
+  // pairs, so an eigenvalue the FP32 phase had not reached is still found.
   bool take_polish(const evsi::PolishJob &job) {
+    const bool clean = status == EVSL_OK && nguard == 0;
     lam = job.lam;
     res = job.res;
     nlock = job.nin;
@@ -881,8 +886,11 @@ struct Slice {
     t_mv += job.t_mv;
     t_ritz += job.t_ritz;
     if (!job.ok) return false;
+    if (!clean) {
+      if (status == EVSL_OK) status = EVSL_ENOCONV;  // begin_fp64_phase then runs
+      return false;
+    }
     fp64_phase = true;
-    status = EVSL_OK;
     done = true;
     return true;
   }

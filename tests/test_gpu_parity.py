@@ -608,6 +608,27 @@ def test_fp32_filter_lanczos_fp64_phase_reaches_fp64_tolerance(ctx, intv_ab):
     assert 1 <= st["npolish"] < 100, st
 
 
+def test_fp32_phase_stopped_short_still_runs_the_stopping_rule(ctx):
+    """16^3 Laplacian + potential, [1.0, 1.15]: max_its = 60 stops the FP32
+    phase before its stopping rule (EVSL_ENOCONV with candidates left). The
+    polish alone may not end such a slice: the FP64 continuation runs the
+    stopping rule from the polished pairs, and every eigenvalue of the slice
+    (dense eigh) is returned at tol with status EVSL_OK."""
+    A = I.laplacian(16, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    w = np.linalg.eigvalsh(A.to_dense())
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    intv = [1.0, 1.15, lo, hi]
+    want = w[(w >= 1.0) & (w <= 1.15)]
+    lam, Y, res, st = ev.evsl_filtered_lanczos(
+        ctx, Ad, intv, _pol(intv), ev.lan_opts(tol=1e-8, seed=2, nev_est=len(want) + 5,
+                                               max_its=60, prec=ev.EVSL_F32))
+    assert st["status"] == 0 and len(lam) == len(want), st
+    assert st["npolish"] >= 100, st
+    assert res.max() <= 1e-8
+    assert_eigs_match(lam, want, max(abs(lo), abs(hi)))
+
+
 def test_fp32_filter_locked_at_tol_skips_the_fp64_phase(ctx):
     """When the FP32 phase locks at the requested tolerance (tol_lo = tol =
     1e-6, above the FP32 filter's floor) every pair already meets it in FP64:

@@ -1033,7 +1033,7 @@ def main():
         copy_probe_main()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.serve or args.filter_only or args.paper_table or args.small or args.pencil:

@@ -127,6 +127,15 @@ inline void *ws(evsl_ctx_t ctx, int slot, size_t bytes) {
   return ctx->ws_ptr[slot];
 }
 
+// Frees workspace slot `slot` (after the stream's pending work).
+inline void ws_release(evsl_ctx_t ctx, int slot) {
+  if ((int)ctx->ws_ptr.size() <= slot || !ctx->ws_ptr[slot]) return;
+  HC(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(ctx, ctx->ws_ptr[slot]);
+  ctx->ws_ptr[slot] = nullptr;
+  ctx->ws_size[slot] = 0;
+}
+
 inline double *pinned(evsl_ctx_t ctx, size_t count) {
   if (ctx->pinned_cap < count) {
     if (ctx->pinned) {

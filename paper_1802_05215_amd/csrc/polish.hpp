@@ -36,12 +36,14 @@ struct PolishJob {
   double t_mv = 0, t_ritz = 0;
 };
 
-// Refines every job (all with the same cc, dd): Rayleigh-Ritz with A on the
-// span of its vectors, then up to max_filter FP64 filter applications, each
-// followed by Rayleigh-Ritz, until every Ritz pair inside the slice meets
-// tol. The filter applications of all unfinished jobs share one block
-// Clenshaw recurrence per iteration. Jobs are taken in groups whose buffers
-// fit half the free device memory.
+// Refines every job (all with the same cc, dd), one after another:
+// Rayleigh-Ritz with A on the span of its vectors, then up to max_filter FP64
+// filter applications (one block Clenshaw recurrence over its k columns),
+// each followed by Rayleigh-Ritz, until every Ritz pair inside the slice
+// meets tol. The job's vectors are refined in place. Device memory, for the
+// job in progress: two FP64 n-vectors per column (its filtered block and a
+// work block), three row-major n x 32 blocks (the recurrence runs over chunks
+// of at most 32 columns), its Gram matrix and partial sums; freed on return.
 void polish(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int max_filter,
             const std::vector<PolishJob *> &jobs);
 

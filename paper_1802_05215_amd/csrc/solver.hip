@@ -850,7 +850,9 @@ struct Slice {
         std::fprintf(stderr, "[evsl] FP32 phase: %d steps, %d pairs locked (%d at tol), %d candidates, status %d\n",
                      its, nlock, at_tol, nguard, status);
       }
-    if (!need || nlock + nguard == 0) return false;
+    // the polish holds two n-vectors per column: it takes at most the lock
+    // capacity (a larger block goes to the continuation directly)
+    if (!need || nlock + nguard == 0 || nlock + nguard > nev_cap) return false;
     job.V = col(0);
     job.ldv = ld;
     job.k = nlock + nguard;

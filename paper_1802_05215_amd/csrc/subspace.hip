@@ -59,8 +59,10 @@ struct SiSlice {
   SiSlice() = default;
   SiSlice(const SiSlice &) = delete;
   SiSlice &operator=(const SiSlice &) = delete;
+  bool own_v = true;  // false in the polish: V is the caller's block
   ~SiSlice() {
-    for (double *p : {V, W, X, Gd, tnp, dots, partial}) dfree(ctx, p);
+    if (own_v) dfree(ctx, V);
+    for (double *p : {W, X, Gd, tnp, dots, partial}) dfree(ctx, p);
     if (hbuf) (void)hipHostFree(hbuf);
   }
 
@@ -104,7 +106,7 @@ struct SiSlice {
   }
 
   // The precision form's FP64 phase on one slice: the block is the job's k
-  // vectors (copied in; written back by take_back).
+  // vectors, refined in place (take_back compacts the in-slice pairs).
   void setup_polish(evsl_ctx_t c, const evsl_csr_t *Am, const evsi::PolishJob &job, double cc_,
                     double dd_) {
     ctx = c;
@@ -121,15 +123,15 @@ struct SiSlice {
     pbound = 0.0;
     for (double x : coef) pbound += std::fabs(x);
     b = job.k;
-    if (b < 1 || b > n || job.ldv < n) fail(EVSL_EINVAL);
+    if (b < 1 || b > n || job.ldv != ((int64_t)n + 63) / 64 * 64) fail(EVSL_EINVAL);
     tol = job.tol;
     seed = job.seed;
+    own_v = false;
+    V = job.V;
     alloc_buffers();
     // refill vectors (rank deficiency only) from a part of the stream that the
     // Lanczos start vectors do not reach
     next_rand = 1 << 20;
-    HC(ctx, hipMemcpy2DAsync(V, sizeof(double) * ld, job.V, sizeof(double) * job.ldv,
-                             sizeof(double) * n, b, hipMemcpyDeviceToDevice, st()));
   }
 
   // Ritz pairs inside the slice after a Rayleigh-Ritz step: count and
@@ -153,8 +155,10 @@ struct SiSlice {
       if (th[j] < tlo || th[j] > thi) continue;
       job.lam.push_back(th[j]);
       job.res.push_back(rs[j]);
-      HC(ctx, hipMemcpyAsync(job.V + (int64_t)t * job.ldv, col(V, j), sizeof(double) * n,
-                             hipMemcpyDeviceToDevice, st()));
+      // in place: column t <= j, and columns below j were read before
+      if (job.V + (int64_t)t * job.ldv != col(V, j))
+        HC(ctx, hipMemcpyAsync(job.V + (int64_t)t * job.ldv, col(V, j), sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st()));
       t++;
     }
     count_in(job.nin, job.nconv);
@@ -168,7 +172,7 @@ struct SiSlice {
 
   void alloc_buffers() {
     ld = ((int64_t)n + 63) / 64 * 64;
-    V = (double *)dalloc(ctx, sizeof(double) * ld * b);
+    if (own_v) V = (double *)dalloc(ctx, sizeof(double) * ld * b);
     W = (double *)dalloc(ctx, sizeof(double) * ld * b);
     X = (double *)dalloc(ctx, sizeof(double) * ld * b);
     Gd = (double *)dalloc(ctx, sizeof(double) * (size_t)b * b);
@@ -339,32 +343,36 @@ struct SiSlice {
 };
 
 // W = p_q(A-hat) V for every column of a batch of slices (in non-increasing
-// degree), as one block Clenshaw recurrence: the columns are gathered into a
-// row-major block, B_k is written over B_{k+2} (four passes per degree step),
-// columns join as k reaches their slice's degree, and the result is
-// scattered back to each slice's W. Buffers: workspace slots 70-74, sized for
-// `cols` columns and degree kmax.
+// degree), as block Clenshaw recurrences over chunks of at most `chunk`
+// consecutive columns: a chunk's columns are gathered into a row-major block,
+// B_k is written over B_{k+2} (four passes per degree step), columns join as k
+// reaches their slice's degree, and the result is scattered back to each
+// slice's W. Buffers: workspace slots 70-74, sized for one chunk and degree
+// kmax.
 struct BlockFilter {
   evsl_ctx_t ctx;
   const evsl_csr_t *A;
   evk::Csr Ac;
   int n;
   double cc, dd;
+  int chunk;
   double *X0 = nullptr, *X1 = nullptr, *Yb = nullptr, *ctab = nullptr;
   double **ptrs = nullptr;
   void *hpin = nullptr;
   std::vector<double> tab;
   std::vector<int> ncs;
 
-  BlockFilter(evsl_ctx_t c, const evsl_csr_t *Am, double cc_, double dd_, int cols, int kmax)
-      : ctx(c), A(Am), n((int)Am->n), cc(cc_), dd(dd_) {
-    const int64_t ldb_max = (cols + 1) / 2 * 2;  // even: two FP64 columns per lane
+  BlockFilter(evsl_ctx_t c, const evsl_csr_t *Am, double cc_, double dd_, int cols, int kmax,
+              int max_chunk)
+      : ctx(c), A(Am), n((int)Am->n), cc(cc_), dd(dd_),
+        chunk(std::max(1, std::min(cols, max_chunk))) {
+    const int64_t ldb_max = (chunk + 1) / 2 * 2;  // even: two FP64 columns per lane
     X0 = (double *)ws(ctx, 70, sizeof(double) * (size_t)n * ldb_max);
     X1 = (double *)ws(ctx, 71, sizeof(double) * (size_t)n * ldb_max);
     Yb = (double *)ws(ctx, 72, sizeof(double) * (size_t)n * ldb_max);
-    ctab = (double *)ws(ctx, 73, sizeof(double) * (size_t)cols * (kmax + 1));
-    ptrs = (double **)ws(ctx, 74, sizeof(double *) * 2 * (size_t)cols);
-    HC(ctx, hipHostMalloc(&hpin, sizeof(double *) * 2 * (size_t)cols, hipHostMallocDefault));
+    ctab = (double *)ws(ctx, 73, sizeof(double) * (size_t)chunk * (kmax + 1));
+    ptrs = (double **)ws(ctx, 74, sizeof(double *) * 2 * (size_t)chunk);
+    HC(ctx, hipHostMalloc(&hpin, sizeof(double *) * 2 * (size_t)chunk, hipHostMallocDefault));
     Ac = to_csr(A);
     attach_col_offsets(ctx, A, Ac);
     ncs.resize(kmax + 2);
@@ -380,51 +388,64 @@ struct BlockFilter {
   double run(const std::vector<SiSlice *> &act) {
     hipStream_t s = ctx->stream;
     const double **hp = (const double **)hpin;
-    int nc = 0, km = 0;
-    for (SiSlice *q : act) {
-      nc += q->b;
-      km = std::max(km, q->deg);
-    }
-    const int64_t ldb = (nc + 1) / 2 * 2;
-    tab.assign((size_t)nc * (km + 1), 0.0);
-    int c = 0;
+    struct ColRef {
+      SiSlice *q;
+      int j;
+    };
+    std::vector<ColRef> all;
     for (SiSlice *q : act)
-      for (int j = 0; j < q->b; ++j, ++c) {
-        std::copy(q->coef.begin(), q->coef.end(), tab.begin() + (size_t)c * (km + 1));
-        hp[c] = q->col(q->V, j);
-        hp[nc + c] = q->col(q->W, j);
-      }
-    for (int j = 0; j <= km; ++j) {
-      int a = 0;
-      for (SiSlice *q : act)
-        if (q->deg >= j) a += q->b;
-      ncs[j] = std::max(a, 1);
-    }
-    // the staging buffers are reused by the next call: wait for the uploads
-    HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
-    HC(ctx, hipMemcpyAsync(ptrs, hp, sizeof(double *) * 2 * nc, hipMemcpyHostToDevice, s));
+      for (int j = 0; j < q->b; ++j) all.push_back({q, j});
+    const int ntot = (int)all.size();
     const double tf0 = now_s();
-    FilterTimer tm(ctx);
-    evk::gather_cols<double>(s, n, nc, (const double *const *)ptrs, X0, ldb);
-    evk::fill_zero<double>(s, (int64_t)n * ldb, X1);
-    evk::fill_zero<double>(s, (int64_t)n * ldb, Yb);
-    double bytes = 2.0 * (double)n * (double)ldb * 8.0;
-    double *bk1 = X1, *bk2 = Yb;
-    for (int k = km; k >= 0; --k) {
-      const double sc = k > 0 ? 2.0 : 1.0;
-      evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2, nullptr,
-                            ldb, ncs[k], ctab, km + 1, k, X0, nullptr, &ctx->blk_sched);
-      bytes += step_bytes(A, ncs[k], 8, 4);
-      std::swap(bk1, bk2);
+    for (int c0 = 0; c0 < ntot; c0 += chunk) {
+      const int nc = std::min(chunk, ntot - c0);
+      int km = 0;
+      for (int c = 0; c < nc; ++c) km = std::max(km, all[c0 + c].q->deg);
+      const int64_t ldb = (nc + 1) / 2 * 2;
+      tab.assign((size_t)nc * (km + 1), 0.0);
+      for (int c = 0; c < nc; ++c) {
+        SiSlice *q = all[c0 + c].q;
+        std::copy(q->coef.begin(), q->coef.end(), tab.begin() + (size_t)c * (km + 1));
+        hp[c] = q->col(q->V, all[c0 + c].j);
+        hp[nc + c] = q->col(q->W, all[c0 + c].j);
+      }
+      // columns in non-increasing degree: those active at step k are a prefix
+      for (int k = 0; k <= km; ++k) {
+        int a = 0;
+        while (a < nc && all[c0 + a].q->deg >= k) ++a;
+        ncs[k] = std::max(a, 1);
+      }
+      HC(ctx, hipMemcpyAsync(ctab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
+                             s));
+      HC(ctx, hipMemcpyAsync(ptrs, hp, sizeof(double *) * 2 * nc, hipMemcpyHostToDevice, s));
+      FilterTimer tm(ctx);
+      evk::gather_cols<double>(s, n, nc, (const double *const *)ptrs, X0, ldb);
+      evk::fill_zero<double>(s, (int64_t)n * ldb, X1);
+      evk::fill_zero<double>(s, (int64_t)n * ldb, Yb);
+      double bytes = 2.0 * (double)n * (double)ldb * 8.0;
+      double *bk1 = X1, *bk2 = Yb;
+      for (int k = km; k >= 0; --k) {
+        const double sc = k > 0 ? 2.0 : 1.0;
+        evk::cheb_blk<double>(s, Ac, evk::STEP_CLEN, sc / dd, -sc * cc / dd, bk1, bk2, bk2,
+                              nullptr, ldb, ncs[k], ctab, km + 1, k, X0, nullptr,
+                              &ctx->blk_sched);
+        bytes += step_bytes(A, ncs[k], 8, 4);
+        std::swap(bk1, bk2);
+      }
+      evk::scatter_cols<double>(s, n, nc, bk1, ldb, (double *const *)(ptrs + nc));
+      tm.stop(km + 1, bytes);
+      // the staging buffers are reused by the next chunk: wait for them
+      HC(ctx, hipStreamSynchronize(s));
     }
-    evk::scatter_cols<double>(s, n, nc, bk1, ldb, (double *const *)(ptrs + nc));
-    tm.stop(km + 1, bytes);
-    HC(ctx, hipStreamSynchronize(s));
     const double tf = now_s() - tf0;
     for (SiSlice *q : act) q->t_mv += tf;
     return tf;
   }
 };
+
+// Columns per block recurrence in the polish: bounds its row-major buffers
+// (3 n x 32 FP64) whatever the block size, at a few percent more reads of A.
+constexpr int kPolishChunk = 32;
 
 // The precision form's FP64 phase on a group of jobs (see polish.hpp).
 void polish_group(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int max_filter,
@@ -467,7 +488,7 @@ void polish_group(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int
     for (size_t t : order)
       if (!ok[t]) act.push_back(&sl[t]);
     if (act.empty()) break;
-    if (!bf) bf.reset(new BlockFilter(ctx, A, cc, dd, cols, kmax));
+    if (!bf) bf.reset(new BlockFilter(ctx, A, cc, dd, cols, kmax, kPolishChunk));
     bf->run(act);
     for (size_t t : order) {
       if (ok[t]) continue;
@@ -494,20 +515,13 @@ namespace evsi {
 
 void polish(evsl_ctx_t ctx, const evsl_csr_t *A, double cc, double dd, int max_filter,
             const std::vector<PolishJob *> &jobs) {
-  if (jobs.empty()) return;
-  // per column: V, W, X of the slice and the three row-major block buffers
-  size_t fr = 0, total = 0;
-  HC(ctx, hipMemGetInfo(&fr, &total));
-  const double per_col = 6.0 * sizeof(double) * (double)(((int64_t)A->n + 63) / 64 * 64);
-  const int cap = (int)std::max(1.0, std::min(0.5 * (double)fr / per_col, 1e9));
-  size_t j0 = 0;
-  while (j0 < jobs.size()) {
-    size_t j1 = j0;
-    int cols = 0;
-    while (j1 < jobs.size() && (j1 == j0 || cols + jobs[j1]->k <= cap)) cols += jobs[j1++]->k;
-    polish_group(ctx, A, cc, dd, max_filter, jobs, j0, j1, cols);
-    j0 = j1;
-  }
+  // one slice at a time: a slice's block (about its eigenvalue count, tens to
+  // hundreds of columns) already shares each read of A over its columns, and
+  // the device memory stays that of one slice
+  for (size_t j = 0; j < jobs.size(); ++j)
+    polish_group(ctx, A, cc, dd, max_filter, jobs, j, j + 1, jobs[j]->k);
+  // the block buffers are the polish's alone: they do not outlive it
+  for (int slot = 70; slot <= 74; ++slot) ws_release(ctx, slot);
 }
 
 }  // namespace evsi
@@ -540,7 +554,7 @@ int evsl_filtered_subspace_batch(evsl_ctx_t ctx, const evsl_csr_t *A, int nslice
     btot += x.b;
     kmax = std::max(kmax, x.deg);
   }
-  BlockFilter bf(ctx, A, cc, dd, btot, kmax);
+  BlockFilter bf(ctx, A, cc, dd, btot, kmax, btot);
   const char *prog_env = std::getenv("EVSL_PROGRESS");
   const bool progress = prog_env && std::atoi(prog_env) > 0;
   int iteration = 0;

@@ -111,8 +111,10 @@ def poisson_stream(seed: int, count: int, rate: float, n_min: float = 1e4, n_max
 # m = max(3 nev_est + 30, 60), lock capacity max(2 nev_est + 40, 100), a
 # basis of (capacity + m + 1) columns with leading dimension n rounded up to
 # 64, workspace slots that grow to the largest use and live until the
-# context is destroyed, and result vectors (at most the lock capacity per
-# slice) held until they are copied out.
+# context is destroyed, result vectors (at most the lock capacity per slice)
+# held until they are copied out, and, in the precision form, the FP64
+# polish (one slice at a time: two n-vectors per column of at most the lock
+# capacity and three row-major blocks of 32 columns, freed when it ends).
 
 _TPB = 256
 
@@ -167,7 +169,16 @@ def footprint_parts(req: Request) -> Dict[str, int]:
     # 16-bit column offsets of the block filter
     batch = 8 * (3 * n * ns + ns * 10001 + 2 * (ns + 1)) + 8 * 2 * ld * m + 2 * nnz + 16
     vectors = 8 * n * cap * ns
-    parts["library"] = ws + batch + ns * per_slice + vectors
+    # precision form: the FP64 polish, one slice at a time and in place, of a
+    # block of at most `cap` columns: its filtered block and work block, the
+    # Gram matrix, the Gram partial sums (4096-row chunks), the dot partials,
+    # and for the recurrence (chunks of at most 32 columns) three row-major
+    # blocks, the coefficient table (degree <= 10000) and the column pointers
+    ch = min(cap, 32)
+    polish = 8 * (2 * ld * cap + cap * cap + ((n + 4095) // 4096) * cap * cap + 3 * cap + 8
+                  + ((n + 2047) // 2048) * cap + 3 * n * ((ch + 1) // 2 * 2) + ch * 10001
+                  + 2 * ch)
+    parts["library"] = ws + batch + ns * per_slice + vectors + polish
     parts["results"] = vectors
     return parts
 

@@ -74,6 +74,9 @@ def test_footprint_grows_with_size_and_target():
     # the basis dominates: at least (capacity + m + 1) FP64 columns per slice
     m, cap = S._lan_sizes(base.nev_plan, base.n)
     assert S.footprint_parts(base)["library"] >= 8 * base.n * (cap + m + 1)
+    # the precision form's FP64 polish (one slice at a time, in place): two
+    # n-vectors per lock-capacity column and three 32-column row-major blocks
+    assert S.footprint_parts(base)["library"] >= 8 * base.n * (cap + m + 1 + 2 * cap + 96)
     # the largest request of the recipe stays within one device's memory
     big = S.Request(0, 0.0, "eigs", 3, 159, 1, target=400)
     assert S.footprint_bytes(big) < 288e9

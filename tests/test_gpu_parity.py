@@ -734,6 +734,39 @@ def test_lanczos_dos_matches_oracle(ctx, N, dim, pot):
             assert abs(a - b) <= 1e-8 * A.n, (x0, x1, sigma, a, b)
 
 
+def test_precision_form_headline_slices_equal_the_oracle(ctx):
+    """The precision form (FP32 filter, FP64 reorthogonalisation, Rayleigh-Ritz,
+    polish and residuals) on slices 0 and 9 of the 100^3 workload's cut, solved
+    together in one batch, against the oracle's FP64 run of them
+    (tests/golden/c2_oracle.json): the same eigenvalue lists (same count, each
+    within 1e-10 relative), residuals <= 1e-8, status EVSL_OK, and the FP64
+    phase ended in the polish (no thick-restart continuation)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")))
+    A = I.laplacian(100, 3, pot_seed=0)
+    Ad = ev.DeviceCsr.from_host(A)
+    lo, hi = ev.evsl_spectrum_bounds(ctx, Ad, 80, 3)
+    normA = max(abs(lo), abs(hi))
+    qs = sorted(int(q) for q in gold["solved"])
+    ivs = [[gold["solved"][str(q)]["interval"][0], gold["solved"][str(q)]["interval"][1], lo, hi]
+           for q in qs]
+    pols = [_pol(iv) for iv in ivs]
+    opts = [ev.lan_opts(tol=1e-8, seed=2 + q, nev_est=gold["solved"][str(q)]["nev_est"],
+                        prec=ev.EVSL_F32) for q in qs]
+    ev.evsl_autotune(ctx, Ad, len(qs), ev.EVSL_F32)
+    outs = ev.evsl_filtered_lanczos_batch(ctx, Ad, ivs, pols, opts)
+    ctx.set_group_width(0)
+    for q, iv, (lam, Y, res, st) in zip(qs, ivs, outs):
+        want = np.array(gold["solved"][str(q)]["eigenvalues"])
+        keep = (lam >= iv[0]) & ((lam < iv[1]) | (q == 9))
+        assert st["status"] == ev.EVSL_OK, st
+        assert 1 <= st["npolish"] < 100, st
+        assert keep.sum() == len(want), (q, int(keep.sum()), len(want))
+        assert_eigs_match(lam[keep], want, normA)
+        assert res.max() <= 1e-8
+
+
 def test_headline_workload_slices_equal_the_oracle(ctx):
     """The 100^3 workload (3-D 7-point Laplacian + U[0,1) potential, KPM cut of
     [0.60, 0.70] into 10 slices, degree 80 x 20 probes) against the oracle's

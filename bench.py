@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-width", type=int, default=-1,
                     help="slices per block filter launch (-1: autotuned, 0: all)")
+    ap.add_argument("--no-precision-leg", action="store_true",
+                    help="skip the precision form's solve of the same cut after the timed "
+                         "FP64 steps")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64",
                     help="filter arithmetic (f32: precision form, FP32 phase then FP64 phase)")
     ap.add_argument("--tol-lo", type=float, default=0.0, help="FP32-phase lock tolerance")
@@ -316,6 +319,45 @@ def cpu_baseline(A, rec, args, c3=None, budget_s=25.0):
             "degree": len(col["coef"]) - 1, "column": col["index"],
             "oracle_s": time.perf_counter() - t0}
     return out
+
+
+def precision_leg(ctx, ev, Ad, args, rec64, value64, log):
+    """The precision form on the same cut, one solve after the timed FP64
+    steps: the FP32-filter Lanczos phase, then the FP64 polish (Rayleigh-Ritz
+    and FP64 filter applications to each slice's block) and, where pairs
+    remain, the FP64 thick-restart continuation, at the same tolerance.
+    Reports its eigenpairs/s beside the FP64 value, whether the counts agree,
+    the FP64 phase each slice took (npolish) and the largest residual. A
+    failure is reported in the leg rather than raised, so that the rest of the
+    line stands."""
+    import copy
+    import torch
+    try:
+        a = copy.copy(args)
+        a.prec = "f32"
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = one_step(ctx, ev, Ad, a)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        v = r["nev"] / dt
+        log(f"[precision] {r['nev']} eigenpairs in {dt:.1f} s ({v:.2f}/s; FP64 {value64:.2f}/s)")
+        return {
+            "workload": "the same cut in the precision form (FP32-filter Lanczos phase, then the "
+                        "FP64 polish and, where pairs remain, the FP64 thick-restart "
+                        f"continuation), tol {args.tol:g}",
+            "value": v, "unit": "eigenpairs/s", "seconds": dt, "nev": r["nev"],
+            "fp64_value": value64, "fp64_nev": rec64["nev"],
+            "ratio_to_fp64": v / value64 if value64 > 0 else None,
+            "counts_equal": r["nev"] == rec64["nev"],
+            "group_width": r["group_width"],
+            "npolish": [p["npolish"] for p in r["per_slice"]],
+            "status": [p["status"] for p in r["per_slice"]],
+            "max_residual": float(r["res"].max()) if r["nev"] else None,
+        }
+    except Exception as e:  # the leg must not cost the measured line
+        log(f"[precision] failed: {e!r}")
+        return {"error": repr(e)}
 
 
 def c3_filter_leg(ctx, ev, args, log):
@@ -1192,6 +1234,9 @@ def main():
         avg_s = fs["seconds"] / fs["launches"]
         out["roofline"]["traffic"] = tb / avg_s / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = tb
+    if (not args.no_precision_leg and N == 100 and args.prec == "f64" and args.method == "tr"
+            and args.mode == "batch" and not args.slices):
+        out["precision_form"] = precision_leg(ctx, ev, Ad, args, rec, value, log)
     c3 = None
     if args.c3 and N == 100:
         c3 = c3_filter_leg(ctx, ev, args, log)

@@ -48,3 +48,12 @@ def test_paper_rows_are_the_printed_table():
     for r in bench.PAPER_ROWS:
         deg, niter, nmv = r[5], r[6], r[7]
         assert deg * niter <= nmv <= deg * (niter + 10) + 2 * r[4] + 100
+
+
+def test_precision_leg_reports_a_failure_instead_of_raising():
+    """Without a device the leg's first GPU call fails: the leg returns the
+    error, so the rest of the bench line stands."""
+    import argparse
+    args = argparse.Namespace(prec="f64", tol=1e-8)
+    r = bench.precision_leg(None, None, None, args, {"nev": 980}, 38.7, lambda m: None)
+    assert set(r) == {"error"} and r["error"]
